@@ -1,0 +1,182 @@
+/*
+ * amytiss.h -- C ABI of libamytiss_hip.so: finite-MDP abstraction and
+ * finite-horizon Bellman synthesis of stochastic control systems on gfx950.
+ *
+ * Method (AMYTISS, arXiv 2005.06191):
+ *   - Abstraction, Sec. 4 (Eq. 4.1) and Alg. 2: for every state cell x and
+ *     input u the next state is f(x_bar, u_bar) + N(0, diag(var)); the
+ *     transition probability to a target cell is the Gaussian mass of that
+ *     cell.  Only cells whose centre lies in the cutting region
+ *     [[mu - x*, mu + x*]] (Sec. 5.2 and its Remark; x* solves
+ *     PDF(x*|0, var_i) = cutoff per dimension) carry probability; every row
+ *     has the same number W = prod_i L_i of slots, L_i = floor(2 x*_i/h_i)+1
+ *     (clamped to the grid).
+ *   - Synthesis, Alg. 4: backward value iteration k = T_d .. 1 for safety,
+ *     reachability and reach-avoid, V_k(x) = max_u sum_{x'} T(x'|x,u) V_{k+1}(x')
+ *     (plus the one-step target mass T0 for reach / reach-avoid), and the
+ *     maximising input per state and step.
+ *   - Two modes: STORED builds the rows once (Alg. 2) and streams them in
+ *     every step; OTF recomputes them inside every step (Sec. 6.1,
+ *     on-the-fly abstraction).
+ *
+ * Readings of points the paper leaves open (each is part of the contract):
+ *   - a state is represented by its cell centre; it belongs to a box when its
+ *     centre does (closed boxes, +-INFINITY allowed);
+ *   - probability mass that leaves the grid is lost (value 0);
+ *   - safety uses the safe box S (default: the whole grid); states outside S
+ *     have value 0;
+ *   - reach and reach-avoid follow Alg. 4; a cell in both T and A counts as
+ *     A; the returned V is 1 on T\A and 0 on A, policy -1 there;
+ *   - policy ties go to the lowest input index;
+ *   - the mean mu = f(x_bar, u_bar) is evaluated in FP64 in the order written
+ *     next to each dynamics kind below, without fused multiply-adds.
+ *
+ * Conventions of every call:
+ *   - all functions return amy_status and never throw; amy_last_error()
+ *     gives a thread-local message for the last failure;
+ *   - the caller owns every struct and buffer; nothing is retained after a
+ *     call returns (the server copies problems at submit);
+ *   - "device" pointers are HIP device memory on the current device; the
+ *     library allocates no device memory on the solve path: it uses the
+ *     caller's workspace, sized by amy_query;
+ *   - problems are validated before any device work; outputs are undefined
+ *     after an error.
+ */
+#ifndef AMYTISS_H
+#define AMYTISS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMY_MAX_DIM 8
+#define AMY_MAX_IN 4
+#define AMY_MAX_PARAMS 128
+
+typedef enum {
+  AMY_OK = 0,
+  AMY_E_INVALID = 1,     /* bad problem or argument                          */
+  AMY_E_NOMEM = 2,       /* workspace / budget too small                     */
+  AMY_E_DEVICE = 3,      /* a HIP runtime call failed                        */
+  AMY_E_UNSUPPORTED = 4, /* valid but not supported by this build            */
+  AMY_E_BUSY = 5,        /* server queue full                                */
+  AMY_E_NOTREADY = 6     /* server: result not ready yet                     */
+} amy_status;
+
+typedef enum { AMY_SAFETY = 0, AMY_REACH = 1, AMY_REACH_AVOID = 2 } amy_spec;
+typedef enum { AMY_MODE_AUTO = 0, AMY_MODE_STORED = 1, AMY_MODE_OTF = 2 } amy_mode;
+
+/* FP64: every mass, sum and value in FP64 (the plain GPU path).
+ * FP32: cell masses and Bellman sums in FP32 (erfc-differenced tails,
+ * compensated outer sums); FP64 kept for the mean and window, the per-row
+ * truncated-tail mass and the last step, whose sums and output are FP64. */
+typedef enum { AMY_FP64 = 0, AMY_FP32 = 1 } amy_precision;
+
+/* Dynamics mu = f(x, u) (x = cell centre, u = input point):
+ *  AMY_DYN_AFFINE    x+ = A x + B u + c; params = A[n*n], B[n*m], c[n]
+ *                    (row-major); mu_i = (sum_j A_ij x_j + c_i) + sum_k B_ik u_k,
+ *                    each sum taken left to right.
+ *  AMY_DYN_UNICYCLE  n = 3, m = 2, u = (v, omega); params = {tau};
+ *                    mu = (x + (tau v) cos th, y + (tau v) sin th, th + tau omega).
+ *  AMY_DYN_ROOM      ring of n rooms, m = 1 shared heater or m = n heaters;
+ *                    params = {alpha, beta, gam, T_e, T_h};
+ *                    mu_i = ((c0 x_i + alpha (x_{i-1} + x_{i+1})) + beta T_e)
+ *                           + u_i (gam (T_h - x_i)),  c0 = (1 - 2 alpha) - beta,
+ *                    indices modulo n (rooms on a circle).
+ *  AMY_DYN_VEHICLE7  n = 7, m = 2: the single-track model of the paper's
+ *                    Sec. 8.3 with its printed right-hand sides, saturations
+ *                    = clamps to the input box; params = {tau, l_wb, m, mu_bar,
+ *                    l_f, l_r, h_cg, I_z, C_Sf, C_Sr, g}. */
+typedef enum {
+  AMY_DYN_AFFINE = 0,
+  AMY_DYN_UNICYCLE = 1,
+  AMY_DYN_ROOM = 2,
+  AMY_DYN_VEHICLE7 = 3
+} amy_dyn_kind;
+
+/* State grid: dimension i has count[i] cells [lo[i] + j h[i], lo[i] + (j+1) h[i]);
+ * states are numbered row-major, the last dimension fastest. */
+typedef struct {
+  int32_t n;
+  int32_t count[AMY_MAX_DIM];
+  double lo[AMY_MAX_DIM];
+  double h[AMY_MAX_DIM];
+} amy_grid;
+
+/* Input set: dimension k is the inclusive linspace lo[k] .. hi[k] with
+ * count[k] points, u = lo + j * ((hi - lo)/(count - 1)); one point is lo.
+ * Inputs are numbered row-major, the last dimension fastest. */
+typedef struct {
+  int32_t m;
+  int32_t count[AMY_MAX_IN];
+  double lo[AMY_MAX_IN];
+  double hi[AMY_MAX_IN];
+} amy_inputs;
+
+/* Closed box; set lo > hi in any dimension for the empty box. */
+typedef struct {
+  double lo[AMY_MAX_DIM];
+  double hi[AMY_MAX_DIM];
+} amy_box;
+
+typedef struct {
+  int32_t kind;        /* amy_dyn_kind */
+  int32_t n_params;
+  double params[AMY_MAX_PARAMS];
+} amy_dynamics;
+
+typedef struct {
+  amy_grid grid;
+  amy_inputs inputs;
+  amy_dynamics dyn;
+  double noise_var[AMY_MAX_DIM]; /* diag of the covariance (variances)       */
+  double cutoff;                 /* gamma >= 0; 0 keeps every cell           */
+  int32_t horizon;               /* T_d >= 0                                 */
+  int32_t spec;                  /* amy_spec                                 */
+  amy_box target;                /* reach / reach-avoid                      */
+  amy_box avoid;                 /* reach-avoid                              */
+  amy_box safe;                  /* safety                                   */
+  int32_t mode;                  /* amy_mode                                 */
+  int32_t precision;             /* amy_precision                            */
+} amy_problem;
+
+typedef struct {
+  int32_t mode_used;             /* AMY_MODE_STORED or AMY_MODE_OTF          */
+  int32_t window[AMY_MAX_DIM];   /* L_i                                      */
+  int32_t kernel;                /* sweep variant: lanes per row (1 or 64)   */
+  int64_t n_x, n_u, rows, W;     /* states, inputs, rows = n_x n_u, slots    */
+  uint64_t workspace_bytes;      /* bytes amy_solve needs for this problem   */
+  uint64_t stored_bytes;         /* of which transition rows (STORED mode)   */
+  double max_row_tail;           /* max over rows of the cut-off mass (FP64) */
+  double tail_bound_E;           /* T_d * max_row_tail: V_{no cut} <= V + E  */
+  double t_build_ms, t_sweeps_ms, t_readout_ms, t_total_ms;
+} amy_info;
+
+/* Validate p and fill sizes, the mode AUTO resolves to for a workspace of
+ * at most ws_budget bytes (0 = unlimited) and the workspace size.  No device
+ * work.  AMY_E_INVALID for a malformed problem; AMY_E_NOMEM when even the
+ * OTF mode needs more than ws_budget. */
+amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_info* out);
+
+/* Solve p on the HIP stream `stream` (hipStream_t; NULL = default stream).
+ * workspace: device memory of ws_bytes >= amy_query's workspace_bytes
+ * (computed with the same budget).  V_out: device double[n_x], V at k = 1.
+ * policy_out: device int16[T_d * n_x] or NULL; entry (k-1)*n_x + x is the
+ * maximising input at step k (-1 where the value is fixed).
+ * info == NULL: the call only enqueues work and returns.  info != NULL: the
+ * call waits for the stream and fills info, including the FP64 tail bound
+ * and the phase times (HIP events on `stream`). */
+amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
+                     double* V_out, int16_t* policy_out, amy_info* info);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* amy_last_error(void);
+
+/* Library version string. */
+const char* amy_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMYTISS_H */

@@ -1,0 +1,195 @@
+"""ctypes binding of libamytiss_hip.so (argument marshalling only).
+
+Every step of the path runs in the HIP library; this module only mirrors
+the C structs of include/amytiss.h, allocates device buffers with PyTorch
+and passes pointers and the current HIP stream.  Loading fails loudly when
+the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamytiss_hip.so")
+
+MAX_DIM, MAX_IN, MAX_PARAMS = 8, 4, 128
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_NOTREADY = range(7)
+STATUS = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "BUSY", 6: "NOTREADY"}
+DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3}
+SPEC = {"safety": 0, "reach": 1, "reach_avoid": 2}
+MODE = {"auto": 0, "stored": 1, "otf": 2}
+MODE_NAME = {v: k for k, v in MODE.items()}
+PREC = {"fp64": 0, "fp32": 1}
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("count", C.c_int32 * MAX_DIM),
+                ("lo", C.c_double * MAX_DIM), ("h", C.c_double * MAX_DIM)]
+
+
+class Inputs(C.Structure):
+    _fields_ = [("m", C.c_int32), ("count", C.c_int32 * MAX_IN),
+                ("lo", C.c_double * MAX_IN), ("hi", C.c_double * MAX_IN)]
+
+
+class Box(C.Structure):
+    _fields_ = [("lo", C.c_double * MAX_DIM), ("hi", C.c_double * MAX_DIM)]
+
+
+class Dynamics(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_params", C.c_int32), ("params", C.c_double * MAX_PARAMS)]
+
+
+class ProblemC(C.Structure):
+    _fields_ = [("grid", Grid), ("inputs", Inputs), ("dyn", Dynamics),
+                ("noise_var", C.c_double * MAX_DIM), ("cutoff", C.c_double),
+                ("horizon", C.c_int32), ("spec", C.c_int32),
+                ("target", Box), ("avoid", Box), ("safe", Box),
+                ("mode", C.c_int32), ("precision", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("mode_used", C.c_int32), ("window", C.c_int32 * MAX_DIM), ("kernel", C.c_int32),
+                ("n_x", C.c_int64), ("n_u", C.c_int64), ("rows", C.c_int64), ("W", C.c_int64),
+                ("workspace_bytes", C.c_uint64), ("stored_bytes", C.c_uint64),
+                ("max_row_tail", C.c_double), ("tail_bound_E", C.c_double),
+                ("t_build_ms", C.c_double), ("t_sweeps_ms", C.c_double),
+                ("t_readout_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            if name == "window":
+                v = [int(x) for x in v]
+            d[name] = v
+        d["mode"] = MODE_NAME.get(self.mode_used, "?")
+        return d
+
+
+class AmyError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"amytiss {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        pp, ip = C.POINTER(ProblemC), C.POINTER(Info)
+        L.amy_query.argtypes = [pp, C.c_uint64, ip]
+        L.amy_query.restype = C.c_int
+        L.amy_solve.argtypes = [pp, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, ip]
+        L.amy_solve.restype = C.c_int
+        L.amy_last_error.restype = C.c_char_p
+        L.amy_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != OK:
+        raise AmyError(status, lib().amy_last_error().decode())
+
+
+def _box(dst, b, n, empty_default):
+    for i in range(MAX_DIM):
+        if b is None:
+            lo, hi = (1.0, -1.0) if empty_default else (-math.inf, math.inf)
+        elif i < n:
+            lo, hi = float(b[0][i]), float(b[1][i])
+        else:
+            lo, hi = -math.inf, math.inf
+        dst.lo[i], dst.hi[i] = lo, hi
+
+
+def to_struct(p, mode=None, precision=None) -> ProblemC:
+    """Marshal a problem description (any object with the fields of
+    workloads.Problem) into the C struct."""
+    s = ProblemC()
+    n, m = len(p.count), len(p.u_count)
+    s.grid.n, s.inputs.m = n, m
+    for i in range(n):
+        s.grid.count[i], s.grid.lo[i], s.grid.h[i] = int(p.count[i]), float(p.lo[i]), float(p.h[i])
+        s.noise_var[i] = float(p.var[i])
+    for k in range(m):
+        s.inputs.count[k], s.inputs.lo[k], s.inputs.hi[k] = (int(p.u_count[k]), float(p.u_lo[k]),
+                                                              float(p.u_hi[k]))
+    s.dyn.kind = DYN[p.dyn]
+    s.dyn.n_params = len(p.params)
+    for k, v in enumerate(p.params):
+        s.dyn.params[k] = float(v)
+    s.cutoff = float(p.cutoff)
+    s.horizon = int(p.horizon)
+    s.spec = SPEC[p.spec]
+    _box(s.target, p.target, n, True)
+    _box(s.avoid, p.avoid, n, True)
+    _box(s.safe, p.safe, n, False)
+    s.mode = MODE[mode or p.mode]
+    s.precision = PREC[precision or p.precision]
+    return s
+
+
+def query(p, budget: int = 0, **kw) -> dict:
+    s = to_struct(p, **kw)
+    info = Info()
+    check(lib().amy_query(C.byref(s), int(budget), C.byref(info)))
+    return info.as_dict()
+
+
+class Result:
+    def __init__(self, V, policy, info):
+        self.V = V            # torch float64 [n_x] on the device
+        self.policy = policy  # torch int16 [T_d, n_x] on the device, or None
+        self.info = info      # dict or None
+
+
+class Solver:
+    """Holds a device workspace for repeated solves of problems of one size."""
+
+    def __init__(self, p, budget: int = 0, device=None, **kw):
+        import torch
+        self.torch = torch
+        self.p = p
+        self.s = to_struct(p, **kw)
+        self.device = torch.device(device or "cuda")
+        info = Info()
+        check(lib().amy_query(C.byref(self.s), int(budget), C.byref(info)))
+        self.plan = info.as_dict()
+        self.ws_bytes = int(info.workspace_bytes)
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        self.ws_ptr = self._ws.data_ptr() + off
+
+    def solve(self, policy: bool = True, info: bool = True, stream=None, out=None) -> Result:
+        torch = self.torch
+        n_x, T = self.p.n_x, self.p.horizon
+        V = out if out is not None else torch.empty(n_x, dtype=torch.float64, device=self.device)
+        pol = torch.empty((T, n_x), dtype=torch.int16, device=self.device) if (policy and T > 0) else None
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        inf = Info() if info else None
+        rc = lib().amy_solve(C.byref(self.s), C.c_void_p(st.cuda_stream), C.c_void_p(self.ws_ptr),
+                             self.ws_bytes, C.c_void_p(V.data_ptr()),
+                             C.c_void_p(pol.data_ptr()) if pol is not None else None,
+                             C.byref(inf) if inf is not None else None)
+        check(rc)
+        return Result(V, pol, inf.as_dict() if inf is not None else None)
+
+
+def solve(p, policy: bool = True, info: bool = True, budget: int = 0, **kw) -> Result:
+    return Solver(p, budget=budget, **kw).solve(policy=policy, info=info)
+
+
+def version() -> str:
+    return lib().amy_version().decode()

@@ -1,0 +1,293 @@
+// amy_device.hpp -- device building blocks of the abstraction + Bellman path.
+//
+//  * Dyn<KIND,N>   : the mean mu = f(x_bar, u_bar) (Alg. 2, first step), split
+//                    into a per-state part (prep) and a per-input part (apply)
+//                    so that the inner input loop only redoes what depends on u.
+//  * window / dim_table : the cutting region of Sec. 5.2 (cells whose centre
+//                    lies in [[mu - x*, mu + x*]]) laid out as a fixed window
+//                    of L_i slots that always lies inside the grid; slots
+//                    outside the kept range carry mass 0.  The 1-D masses
+//                    Phi(b) - Phi(a) of the L_i slots are built from L_i + 1
+//                    edge values erfc(|z|/sqrt 2): a diagonal covariance makes
+//                    the cell mass of Alg. 1 a product of these 1-D masses.
+//  * contract      : Alg. 4's row sum  sum_{x' in window} T(x'|x,u) V(x')
+//                    evaluated dimension by dimension (a tensor contraction of
+//                    the 1-D tables with the window of V), which needs about
+//                    W (1 + 1/L_n + ...) multiply-adds instead of 2W.
+// Everything here is compiled with -ffp-contract=off; fused multiply-adds
+// appear only where written (fma_).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "amy_plan.hpp"
+
+#define AMY_DYN_AFFINE_ 0
+#define AMY_DYN_UNICYCLE_ 1
+#define AMY_DYN_ROOM_ 2
+#define AMY_DYN_VEHICLE7_ 3
+
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Renumber them so that XCD x receives one contiguous run of logical blocks:
+// neighbouring states, whose windows overlap, then share an L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G) {
+  const uint32_t q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// Centre of the state's cell, per dimension (state numbering: last dim fastest).
+template <int N>
+__device__ __forceinline__ void state_centre(const DevProblem& P, uint32_t s, double* x) {
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    const uint32_t c = (uint32_t)P.count[i];
+    const uint32_t q = s / c;
+    const uint32_t j = s - q * c;
+    s = q;
+    x[i] = P.lo[i] + ((double)j + 0.5) * P.h[i];
+  }
+}
+
+// Input points as an odometer over the m input dimensions (last fastest).
+struct InputWalk {
+  int dig[AMY_MAXI];
+  __device__ __forceinline__ void reset() {
+#pragma unroll
+    for (int k = 0; k < AMY_MAXI; ++k) dig[k] = 0;
+  }
+  __device__ __forceinline__ void values(const DevProblem& P, double* u) const {
+#pragma unroll
+    for (int k = 0; k < AMY_MAXI; ++k)
+      u[k] = (k < P.m) ? ((P.ucount[k] == 1) ? P.ulo[k] : P.ulo[k] + (double)dig[k] * P.ustep[k]) : 0.0;
+  }
+  __device__ __forceinline__ void next(const DevProblem& P) {
+    bool carry = true;
+#pragma unroll
+    for (int k = AMY_MAXI - 1; k >= 0; --k) {
+      if (carry && k < P.m) {
+        if (++dig[k] >= P.ucount[k]) dig[k] = 0;
+        else carry = false;
+      }
+    }
+  }
+};
+
+// ----------------------------------------------------------------- dynamics
+
+template <int KIND, int N>
+struct Dyn;
+
+template <int N>
+struct Dyn<AMY_DYN_AFFINE_, N> {
+  struct State { double s[N]; };
+  __device__ __forceinline__ static void prep(const DevProblem& P, const double* x, State& st) {
+    const double* A = P.params;
+    const double* c = P.params + N * N + N * P.m;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s = s + A[i * N + j] * x[j];
+      st.s[i] = s + c[i];
+    }
+  }
+  __device__ __forceinline__ static void apply(const DevProblem& P, const State& st, const double*,
+                                               const double* u, double* mu) {
+    const double* B = P.params + N * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < AMY_MAXI; ++k)
+        if (k < P.m) t = t + B[i * P.m + k] * u[k];
+      mu[i] = st.s[i] + t;
+    }
+  }
+};
+
+template <>
+struct Dyn<AMY_DYN_UNICYCLE_, 3> {
+  struct State { double c, s; };
+  __device__ __forceinline__ static void prep(const DevProblem&, const double* x, State& st) {
+    st.c = cos(x[2]);
+    st.s = sin(x[2]);
+  }
+  __device__ __forceinline__ static void apply(const DevProblem& P, const State& st, const double* x,
+                                               const double* u, double* mu) {
+    const double tau = P.params[0];
+    const double a = tau * u[0];
+    mu[0] = x[0] + a * st.c;
+    mu[1] = x[1] + a * st.s;
+    mu[2] = x[2] + tau * u[1];
+  }
+};
+
+template <int N>
+struct Dyn<AMY_DYN_ROOM_, N> {
+  struct State { double s[N], g[N]; };
+  __device__ __forceinline__ static void prep(const DevProblem& P, const double* x, State& st) {
+    const double al = P.params[0], be = P.params[1], ga = P.params[2], Te = P.params[3],
+                 Th = P.params[4];
+    const double c0 = (1.0 - 2.0 * al) - be;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double left = x[(i + N - 1) % N], right = x[(i + 1) % N];
+      st.s[i] = (c0 * x[i] + al * (left + right)) + be * Te;
+      st.g[i] = ga * (Th - x[i]);
+    }
+  }
+  __device__ __forceinline__ static void apply(const DevProblem& P, const State& st, const double*,
+                                               const double* u, double* mu) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double ui = (P.m == 1) ? u[0] : u[i < AMY_MAXI ? i : 0];
+      mu[i] = st.s[i] + ui * st.g[i];
+    }
+  }
+};
+
+template <>
+struct Dyn<AMY_DYN_VEHICLE7_, 7> {
+  struct State { int unused; };
+  __device__ __forceinline__ static void prep(const DevProblem&, const double*, State&) {}
+  __device__ __forceinline__ static void apply(const DevProblem& P, const State&, const double* x,
+                                               const double* u, double* mu) {
+    const double* q = P.params;
+    const double tau = q[0], lwb = q[1], mass = q[2], mub = q[3], lf = q[4], lr = q[5];
+    const double hcg = q[6], Iz = q[7], CSf = q[8], CSr = q[9], g = q[10];
+    const double x3 = x[2], x4 = x[3], x5 = x[4], x6 = x[5], x7 = x[6];
+    const double v1 = fmin(fmax(u[0], P.ulo[0]), P.uhi[0]);
+    const double v2 = fmin(fmax(u[1], P.ulo[1]), P.uhi[1]);
+    double f1, f2, f5, f6, f7;
+    if (fabs(x4) < 0.1) {
+      f1 = x4 * cos(x5);
+      f2 = x4 * sin(x5);
+      f5 = (x4 / lwb) * tan(x3);
+      const double c3 = cos(x3);
+      f6 = (v2 / lwb) * tan(x3) + (x4 / (lwb * (c3 * c3))) * v1;
+      f7 = 0.0;
+    } else {
+      const double Ff = g * lr - v2 * hcg;
+      const double Fr = g * lf + v2 * hcg;
+      f1 = x4 * cos(x5 + x7);
+      f2 = x4 * sin(x5 + x7);
+      f5 = x6;
+      const double r64 = x6 / x4;
+      f6 = ((mub * mass) / (Iz * (lr + lf))) *
+           ((lf * CSf * Ff * x3 + (lr * CSr * Fr - lf * CSf * Ff) * x7) -
+            (lf * lf * CSf * Ff + lr * lr * CSr * Fr) * r64);
+      f7 = (mub / (x4 * (lr + lf))) *
+               ((CSf * Ff * x3 + (CSr * Fr + CSf * Ff) * x7) - (lf * CSf * Ff - lr * CSr * Fr) * r64) -
+           x6;
+    }
+    mu[0] = x[0] + tau * f1;
+    mu[1] = x[1] + tau * f2;
+    mu[2] = x3 + tau * v1;
+    mu[3] = x4 + tau * v2;
+    mu[4] = x5 + tau * f5;
+    mu[5] = x6 + tau * f6;
+    mu[6] = x7 + tau * f7;
+  }
+};
+
+// ---------------------------------------------------------- cutting window
+
+// Kept cells of dimension i for mean mu: [jlo, b-1] (empty when b == jlo),
+// and the origin o of the fixed L_i-slot window, o <= jlo, o + L_i <= n_i.
+struct Win { int jlo, b, o; };
+
+__device__ __forceinline__ Win window_1d(const DevProblem& P, int i, double mu) {
+  const int n = P.count[i], L = P.L[i];
+  Win w;
+  if (P.nocut) {
+    w.jlo = 0;
+    w.b = n;
+  } else {
+    // cell j is kept iff its centre lo + (j + 1/2) h lies in [mu - x*, mu + x*]
+    double tl = ((mu - P.xstar[i]) - P.lo[i]) * P.inv_h[i] - 0.5;
+    double th = ((mu + P.xstar[i]) - P.lo[i]) * P.inv_h[i] - 0.5;
+    tl = fmin(fmax(tl, -1.0), (double)n);
+    th = fmin(fmax(th, -2.0), (double)n);
+    const int jlo = max(0, (int)ceil(tl));
+    int jhi = min(n - 1, (int)floor(th));
+    jhi = min(jhi, jlo + L - 1);  // allocation bound, for rounding at exact ties
+    w.jlo = jlo;
+    w.b = max(jhi + 1, jlo);
+  }
+  w.o = min(w.jlo, n - L);
+  return w;
+}
+
+__device__ __forceinline__ float ec_of(double z, float) {
+  return erfcf((float)(fabs(z) * 0.70710678118654752440));
+}
+__device__ __forceinline__ double ec_of(double z, double) {
+  return erfc(fabs(z) * 0.70710678118654752440);
+}
+
+// Phi(z1) - Phi(z0) from e = erfc(|z|/sqrt 2): upper-tail difference when
+// both edges are >= 0, lower-tail difference when both are <= 0, else
+// 1 minus both tails.  Tail cells keep their relative accuracy.
+template <class MT>
+__device__ __forceinline__ MT mass_of(double z0, MT e0, double z1, MT e1) {
+  if (z0 >= 0.0) return MT(0.5) * (e0 - e1);
+  if (z1 <= 0.0) return MT(0.5) * (e1 - e0);
+  return MT(1) - MT(0.5) * (e0 + e1);
+}
+
+__device__ __forceinline__ double edge_z(const DevProblem& P, int i, int E, double mu) {
+  return ((P.lo[i] + (double)E * P.h[i]) - mu) * P.inv_sigma[i];
+}
+
+// 1-D masses of the L_i window slots of dimension i into t[k*ts]; returns o.
+template <class MT>
+__device__ __forceinline__ int dim_table(const DevProblem& P, int i, double mu, MT* t, int ts) {
+  const Win w = window_1d(P, i, mu);
+  const int L = P.L[i];
+  double zp = edge_z(P, i, min(max(w.o, w.jlo), w.b), mu);
+  MT ep = ec_of(zp, MT());
+  for (int k = 0; k < L; ++k) {
+    const double z = edge_z(P, i, min(max(w.o + k + 1, w.jlo), w.b), mu);
+    const MT e = ec_of(z, MT());
+    t[k * ts] = mass_of(zp, ep, z, e);
+    zp = z;
+    ep = e;
+  }
+  return w.o;
+}
+
+// FP64 mass of [edge ea, edge eb] of dimension i.
+__device__ __forceinline__ double mass_edges(const DevProblem& P, int i, int ea, int eb, double mu) {
+  const double za = edge_z(P, i, ea, mu), zb = edge_z(P, i, eb, mu);
+  return mass_of(za, ec_of(za, 0.0), zb, ec_of(zb, 0.0));
+}
+
+// ------------------------------------------------------------- contraction
+
+// sum over the window of prod_i t_i[k_i] * V[base + sum_i k_i stride_i],
+// innermost dimension first.  COMP: Kahan-compensated outermost sum.
+template <int D, int N, class MT, class AT, class VT, bool COMP>
+__device__ __forceinline__ AT contract(const DevProblem& P, const MT* __restrict__ t, int ts,
+                                       const VT* __restrict__ V, int64_t base) {
+  const int L = P.L[D];
+  const MT* td = t + P.Loff[D] * ts;
+  AT acc = AT(0), c = AT(0);
+  for (int k = 0; k < L; ++k) {
+    AT inner;
+    if constexpr (D == N - 1) inner = AT(V[base + k]);
+    else inner = contract<D + 1, N, MT, AT, VT, COMP>(P, t, ts, V, base + (int64_t)k * P.stride[D]);
+    if constexpr (COMP && D == 0) {
+      const AT y = AT(td[k * ts]) * inner - c;
+      const AT s2 = acc + y;
+      c = (s2 - acc) - y;
+      acc = s2;
+    } else {
+      acc = fma_(AT(td[k * ts]), inner, acc);
+    }
+  }
+  return acc;
+}

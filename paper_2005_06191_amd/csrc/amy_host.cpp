@@ -1,0 +1,331 @@
+// amy_host.cpp -- C ABI: validation, planning, workspace layout and the
+// single-problem solve driver (one HIP stream, no allocation).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/amytiss.h"
+#include "amy_host.hpp"
+#include "amy_kernels.hpp"
+
+static thread_local std::string g_err;
+
+amy_status amy_fail(amy_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+amy_status amy_hip_fail(hipError_t e, const char* what) {
+  return amy_fail(AMY_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* amy_last_error(void) { return g_err.c_str(); }
+extern "C" const char* amy_version(void) { return "amytiss-hip 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------- planning
+
+static const double SQRT_2PI = 2.5066282746310002;
+
+// Cutting half-width x* of Sec. 5.2: the 1-D normal density with variance
+// var equals the cutoff gamma at +-x*.
+static double xstar_of(double var, double cutoff) {
+  const double s = sqrt(var);
+  const double t = (cutoff * s) * SQRT_2PI;
+  return s * sqrt(-2.0 * log(t));
+}
+
+static int expected_params(const amy_problem* p) {
+  const int n = p->grid.n, m = p->inputs.m;
+  switch (p->dyn.kind) {
+    case AMY_DYN_AFFINE: return n * n + n * m + n;
+    case AMY_DYN_UNICYCLE: return 1;
+    case AMY_DYN_ROOM: return 5;
+    case AMY_DYN_VEHICLE7: return 11;
+  }
+  return -1;
+}
+
+amy_status amy_validate(const amy_problem* p) {
+  if (!p) return amy_fail(AMY_E_INVALID, "problem is NULL");
+  const int n = p->grid.n, m = p->inputs.m;
+  if (n < 1 || n > AMY_MAX_DIM) return amy_fail(AMY_E_INVALID, "grid.n=%d not in [1,%d]", n, AMY_MAX_DIM);
+  if (m < 1 || m > AMY_MAX_IN) return amy_fail(AMY_E_INVALID, "inputs.m=%d not in [1,%d]", m, AMY_MAX_IN);
+  double nx = 1;
+  for (int i = 0; i < n; ++i) {
+    if (p->grid.count[i] < 1) return amy_fail(AMY_E_INVALID, "grid.count[%d]=%d < 1", i, p->grid.count[i]);
+    if (!(p->grid.h[i] > 0) || !isfinite(p->grid.h[i])) return amy_fail(AMY_E_INVALID, "grid.h[%d] <= 0", i);
+    if (!isfinite(p->grid.lo[i])) return amy_fail(AMY_E_INVALID, "grid.lo[%d] not finite", i);
+    if (!(p->noise_var[i] > 0) || !isfinite(p->noise_var[i]))
+      return amy_fail(AMY_E_INVALID, "noise_var[%d] <= 0", i);
+    nx *= p->grid.count[i];
+  }
+  if (nx >= 2147483647.0) return amy_fail(AMY_E_UNSUPPORTED, "n_x=%.0f >= 2^31 states", nx);
+  double nu = 1;
+  for (int k = 0; k < m; ++k) {
+    if (p->inputs.count[k] < 1) return amy_fail(AMY_E_INVALID, "inputs.count[%d] < 1", k);
+    if (!isfinite(p->inputs.lo[k]) || !isfinite(p->inputs.hi[k]))
+      return amy_fail(AMY_E_INVALID, "inputs bounds of dim %d not finite", k);
+    if (p->inputs.count[k] > 1 && !(p->inputs.hi[k] >= p->inputs.lo[k]))
+      return amy_fail(AMY_E_INVALID, "inputs.hi[%d] < inputs.lo[%d]", k, k);
+    nu *= p->inputs.count[k];
+  }
+  if (nu > 32767) return amy_fail(AMY_E_UNSUPPORTED, "n_u=%.0f > 32767 (int16 policy)", nu);
+  if (!(p->cutoff >= 0) || !isfinite(p->cutoff)) return amy_fail(AMY_E_INVALID, "cutoff < 0");
+  if (p->cutoff > 0) {
+    for (int i = 0; i < n; ++i) {
+      const double t = (p->cutoff * sqrt(p->noise_var[i])) * SQRT_2PI;
+      if (!(t < 1.0))
+        return amy_fail(AMY_E_INVALID, "cutoff %g is at or above the peak density of dimension %d",
+                        p->cutoff, i);
+    }
+  }
+  if (p->horizon < 0) return amy_fail(AMY_E_INVALID, "horizon < 0");
+  if (p->spec < AMY_SAFETY || p->spec > AMY_REACH_AVOID) return amy_fail(AMY_E_INVALID, "bad spec");
+  if (p->mode < AMY_MODE_AUTO || p->mode > AMY_MODE_OTF) return amy_fail(AMY_E_INVALID, "bad mode");
+  if (p->precision != AMY_FP64 && p->precision != AMY_FP32) return amy_fail(AMY_E_INVALID, "bad precision");
+  const int ep = expected_params(p);
+  if (ep < 0) return amy_fail(AMY_E_INVALID, "bad dynamics kind %d", p->dyn.kind);
+  if (p->dyn.kind == AMY_DYN_UNICYCLE && (n != 3 || m != 2))
+    return amy_fail(AMY_E_INVALID, "unicycle needs n=3, m=2");
+  if (p->dyn.kind == AMY_DYN_VEHICLE7 && (n != 7 || m != 2))
+    return amy_fail(AMY_E_INVALID, "vehicle7 needs n=7, m=2");
+  if (p->dyn.kind == AMY_DYN_ROOM && !(m == 1 || m == n))
+    return amy_fail(AMY_E_INVALID, "room needs m=1 (shared heater) or m=n");
+  if (p->dyn.n_params != ep)
+    return amy_fail(AMY_E_INVALID, "dynamics needs %d params, got %d", ep, p->dyn.n_params);
+  for (int k = 0; k < p->dyn.n_params; ++k)
+    if (!isfinite(p->dyn.params[k])) return amy_fail(AMY_E_INVALID, "param %d not finite", k);
+  return AMY_OK;
+}
+
+void amy_make_plan(const amy_problem* p, Plan* pl) {
+  DevProblem& D = pl->dev;
+  memset(&D, 0, sizeof D);
+  const int n = p->grid.n, m = p->inputs.m;
+  D.n = n;
+  D.m = m;
+  D.kind = p->dyn.kind;
+  D.spec = p->spec;
+  D.nocut = (p->cutoff == 0.0);
+  int64_t nx = 1;
+  for (int i = n - 1; i >= 0; --i) {
+    D.stride[i] = nx;
+    nx *= p->grid.count[i];
+  }
+  D.n_x = (int32_t)nx;
+  int64_t W = 1;
+  int off = 0;
+  for (int i = 0; i < n; ++i) {
+    D.count[i] = p->grid.count[i];
+    D.lo[i] = p->grid.lo[i];
+    D.h[i] = p->grid.h[i];
+    D.inv_h[i] = 1.0 / p->grid.h[i];
+    const double sigma = sqrt(p->noise_var[i]);
+    D.inv_sigma[i] = 1.0 / sigma;
+    int L = p->grid.count[i];
+    if (!D.nocut) {
+      D.xstar[i] = xstar_of(p->noise_var[i], p->cutoff);
+      const double l = floor(2.0 * D.xstar[i] / p->grid.h[i]) + 1.0;
+      if (l < (double)L) L = (int)l;
+    } else {
+      D.xstar[i] = INFINITY;
+    }
+    D.L[i] = L;
+    D.Loff[i] = off;
+    off += L;
+    W *= L;
+  }
+  D.Loff[n] = off;
+  D.W = (int32_t)(W < 2147483647 ? W : 2147483647);
+  int nu = 1;
+  for (int k = 0; k < m; ++k) {
+    D.ucount[k] = p->inputs.count[k];
+    D.ulo[k] = p->inputs.lo[k];
+    D.uhi[k] = p->inputs.hi[k];
+    D.ustep[k] = (p->inputs.count[k] > 1) ? (p->inputs.hi[k] - p->inputs.lo[k]) / (double)(p->inputs.count[k] - 1)
+                                          : 0.0;
+    nu *= p->inputs.count[k];
+  }
+  D.n_u = nu;
+  for (int i = 0; i < AMY_MAX_DIM; ++i) {
+    D.tlo[i] = p->target.lo[i];
+    D.thi[i] = p->target.hi[i];
+    D.alo[i] = p->avoid.lo[i];
+    D.ahi[i] = p->avoid.hi[i];
+    D.slo[i] = p->safe.lo[i];
+    D.shi[i] = p->safe.hi[i];
+  }
+  for (int k = 0; k < p->dyn.n_params; ++k) D.params[k] = p->dyn.params[k];
+  pl->W = W;
+  pl->rows = nx * (int64_t)nu;
+  pl->f64 = (p->precision == AMY_FP64);
+}
+
+static inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// Workspace: labels | V0 | V1 | tail max | (stored: T rows | origins).
+// T is kept in the precision of the path (FP32 rows for the FP32 path,
+// as the paper's own memory figures imply; FP64 rows for the plain path).
+void amy_layout(Plan* pl, int mode) {
+  const DevProblem& D = pl->dev;
+  const uint64_t nx = (uint64_t)D.n_x;
+  const uint64_t vs = pl->f64 ? 8 : 4;
+  uint64_t o = 0;
+  pl->off_label = o;  o = align256(o + nx);
+  pl->off_v0 = o;     o = align256(o + nx * vs);
+  pl->off_v1 = o;     o = align256(o + nx * vs);
+  pl->off_tail = o;   o = align256(o + 8);
+  pl->stored_bytes = 0;
+  if (mode == AMY_MODE_STORED) {
+    const uint64_t tiles = (nx + 63) / 64;
+    const uint64_t rows_p = tiles * 64 * (uint64_t)D.n_u;
+    pl->off_T = o;    o = align256(o + rows_p * (uint64_t)pl->W * vs);
+    pl->off_org = o;  o = align256(o + rows_p * 4);
+    pl->stored_bytes = o - pl->off_T;
+  }
+  pl->mode = mode;
+  pl->ws_bytes = o;
+}
+
+// AUTO: on MI355X the on-the-fly sweep costs ~3W flops plus the edge
+// erfc's per row, the stored sweep 4W (8W) bytes of HBM traffic; at the
+// chip's ~20 flop/byte balance OTF wins for every built-in family, so AUTO
+// takes OTF.  STORED is used only when asked for explicitly.
+amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
+  amy_make_plan(p, pl);
+  int mode = p->mode == AMY_MODE_AUTO ? AMY_MODE_OTF : p->mode;
+  if (mode == AMY_MODE_STORED && (int64_t)pl->dev.W != pl->W)
+    return amy_fail(AMY_E_UNSUPPORTED, "window of %lld slots too large to store", (long long)pl->W);
+  amy_layout(pl, mode);
+  if (budget && pl->ws_bytes > budget)
+    return amy_fail(AMY_E_NOMEM, "workspace %llu B exceeds budget %llu B",
+                    (unsigned long long)pl->ws_bytes, (unsigned long long)budget);
+  // the lane kernel keeps each lane's 1-D tables in LDS
+  if (amy_lane_lds_bytes(pl->dev, pl->f64) > 64 * 1024)
+    return amy_fail(AMY_E_UNSUPPORTED, "window tables need %zu B of LDS (> 64 KiB)",
+                    amy_lane_lds_bytes(pl->dev, pl->f64));
+  return AMY_OK;
+}
+
+static void fill_info(const amy_problem* p, const Plan& pl, amy_info* info) {
+  memset(info, 0, sizeof *info);
+  info->mode_used = pl.mode;
+  for (int i = 0; i < p->grid.n; ++i) info->window[i] = pl.dev.L[i];
+  info->kernel = 1;
+  info->n_x = pl.dev.n_x;
+  info->n_u = pl.dev.n_u;
+  info->rows = pl.rows;
+  info->W = pl.W;
+  info->workspace_bytes = pl.ws_bytes;
+  info->stored_bytes = pl.stored_bytes;
+}
+
+extern "C" amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_info* out) {
+  amy_status st = amy_validate(p);
+  if (st != AMY_OK) return st;
+  Plan pl;
+  st = amy_resolve(p, ws_budget, &pl);
+  if (st != AMY_OK) return st;
+  if (out) fill_info(p, pl, out);
+  return AMY_OK;
+}
+
+// ------------------------------------------------------------------ solve
+
+amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol,
+                       int horizon, bool want_tail, Timing* tm) {
+  const DevProblem& D = pl.dev;
+  char* base = (char*)ws;
+  uint8_t* label = (uint8_t*)(base + pl.off_label);
+  void* Vb[2] = {base + pl.off_v0, base + pl.off_v1};
+  unsigned long long* tailmax = (unsigned long long*)(base + pl.off_tail);
+  hipError_t e;
+  if (tm) hipEventRecord(tm->ev[0], st);
+  if ((e = amy_launch_init(D, label, Vb[0], pl.f64, horizon == 0 ? V_out : nullptr, tailmax, st)) != hipSuccess)
+    return amy_hip_fail(e, "init kernel");
+  if (want_tail && (e = amy_launch_tail(D, label, tailmax, st)) != hipSuccess)
+    return amy_hip_fail(e, "tail kernel");
+  const bool stored = (pl.mode == AMY_MODE_STORED);
+  if (stored && horizon > 0) {
+    if ((e = amy_launch_build(D, pl.f64, label, base + pl.off_T, (int32_t*)(base + pl.off_org), st)) !=
+        hipSuccess)
+      return amy_hip_fail(e, "build kernel");
+  }
+  if (tm) hipEventRecord(tm->ev[1], st);
+  int cur = 0;
+  for (int k = horizon; k >= 1; --k) {
+    const bool last = (k == 1);
+    const SweepKind sk = pl.f64 ? SWEEP_F64 : (last ? SWEEP_F32_LAST : SWEEP_F32);
+    void* out = last ? (void*)V_out : Vb[cur ^ 1];
+    int16_t* pk = pol ? pol + (int64_t)(k - 1) * D.n_x : nullptr;
+    if (stored)
+      e = amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
+                                  label, pk, st);
+    else
+      e = amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk, st);
+    if (e != hipSuccess) return amy_hip_fail(e, "sweep kernel");
+    cur ^= 1;
+  }
+  if (tm) {
+    hipEventRecord(tm->ev[2], st);
+    hipEventRecord(tm->ev[3], st);
+  }
+  return AMY_OK;
+}
+
+extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
+                                double* V_out, int16_t* policy_out, amy_info* info) {
+  amy_status st = amy_validate(p);
+  if (st != AMY_OK) return st;
+  Plan pl;
+  st = amy_resolve(p, ws_bytes, &pl);
+  if (st != AMY_OK) return st;
+  if (!workspace || !V_out) return amy_fail(AMY_E_INVALID, "workspace or V_out is NULL");
+  if (((uintptr_t)workspace & 255) != 0) return amy_fail(AMY_E_INVALID, "workspace not 256-byte aligned");
+  hipStream_t hs = (hipStream_t)stream;
+  Timing tm;
+  Timing* tp = nullptr;
+  if (info) {
+    for (int i = 0; i < 4; ++i) {
+      hipError_t e = hipEventCreate(&tm.ev[i]);
+      if (e != hipSuccess) return amy_hip_fail(e, "hipEventCreate");
+    }
+    tp = &tm;
+  }
+  st = amy_enqueue(pl, hs, workspace, V_out, policy_out, p->horizon, info != nullptr, tp);
+  if (st == AMY_OK && info) {
+    hipError_t e = hipEventSynchronize(tm.ev[3]);
+    if (e != hipSuccess) st = amy_hip_fail(e, "solve");
+    else {
+      fill_info(p, pl, info);
+      unsigned long long bits = 0;
+      e = hipMemcpy(&bits, (char*)workspace + pl.off_tail, 8, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) st = amy_hip_fail(e, "tail readback");
+      double t;
+      memcpy(&t, &bits, 8);
+      info->max_row_tail = t;
+      info->tail_bound_E = t * p->horizon;
+      float ms;
+      hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]);
+      info->t_build_ms = ms;
+      hipEventElapsedTime(&ms, tm.ev[1], tm.ev[2]);
+      info->t_sweeps_ms = ms;
+      hipEventElapsedTime(&ms, tm.ev[2], tm.ev[3]);
+      info->t_readout_ms = ms;
+      hipEventElapsedTime(&ms, tm.ev[0], tm.ev[3]);
+      info->t_total_ms = ms;
+    }
+  }
+  if (tp)
+    for (int i = 0; i < 4; ++i) hipEventDestroy(tm.ev[i]);
+  return st;
+}

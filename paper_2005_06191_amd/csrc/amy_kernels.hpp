@@ -1,0 +1,27 @@
+// amy_kernels.hpp -- host-side entry points of the kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "amy_plan.hpp"
+
+enum SweepKind {
+  SWEEP_F64 = 0,      // FP64 masses, sums and values
+  SWEEP_F32 = 1,      // FP32 masses and sums, FP32 values in and out
+  SWEEP_F32_LAST = 2  // FP32 masses, FP64 sums, FP32 values in, FP64 out (k = 1)
+};
+
+hipError_t amy_launch_init(const DevProblem& P, uint8_t* label, void* V0, bool v0_double, double* Vout,
+                           unsigned long long* tailmax, hipStream_t st);
+hipError_t amy_launch_copy_out(int64_t n, const void* src, bool src_double, double* dst, hipStream_t st);
+hipError_t amy_launch_tail(const DevProblem& P, const uint8_t* label, unsigned long long* tailmax,
+                           hipStream_t st);
+hipError_t amy_launch_sweep_otf(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                                const uint8_t* label, int16_t* pol, hipStream_t st);
+hipError_t amy_launch_build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,
+                            hipStream_t st);
+hipError_t amy_launch_sweep_stored(const DevProblem& P, SweepKind sk, const void* T, const int32_t* org,
+                                   const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                                   hipStream_t st);
+size_t amy_lane_lds_bytes(const DevProblem& P, bool f64);

@@ -1,0 +1,96 @@
+"""CPU checks of the C ABI: the library loads, exports every declared
+symbol, and validates problems before any device work."""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for m in re.finditer(r"\b(amy_\w+)\s*\(", txt):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def A():
+    import paper_2005_06191_amd as A
+    A.binding.lib()
+    return A
+
+
+def test_every_declared_symbol_is_exported(A):
+    names = _declared()
+    assert {"amy_query", "amy_solve", "amy_last_error"} <= names
+    lib = ctypes.CDLL(A.binding.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version(A):
+    assert "gfx950" in A.version()
+
+
+def test_query_sizes_match_the_window_rule(A, orc):
+    # L_i = floor(2 x*_i / h_i) + 1, clamped to the grid
+    for p in (W.linear2d(), W.unicycle3d(), W.room5d(), W.vehicle7d()):
+        q = A.query(p)
+        for i in range(p.n):
+            L = min(p.count[i], int(math.floor(2 * orc.xstar(p.var[i], p.cutoff) / p.h[i])) + 1)
+            assert q["window"][i] == L
+        assert q["W"] == math.prod(q["window"][:p.n])
+        assert q["rows"] == p.n_x * p.n_u
+
+
+def test_query_workspace_and_modes(A):
+    p = W.room5d()
+    otf = A.query(p.with_(mode="otf"))
+    st = A.query(p.with_(mode="stored"))
+    assert otf["mode"] == "otf" and st["mode"] == "stored"
+    assert otf["stored_bytes"] == 0
+    # FP32 stored rows: 64-state tiles x n_u x W x 4 B (+ int32 origins)
+    tiles = (p.n_x + 63) // 64
+    assert st["stored_bytes"] >= tiles * 64 * p.n_u * st["W"] * 4
+    assert A.query(p.with_(mode="auto"))["mode"] == "otf"
+    with pytest.raises(A.AmyError) as e:
+        A.query(p.with_(mode="stored"), budget=1 << 30)
+    assert e.value.status == A.binding.E_NOMEM
+
+
+BAD = [
+    ("zero variance", dict(var=(0.0, 0.01))),
+    ("negative h", dict(h=(-0.04, 0.04))),
+    ("zero count", dict(count=(0, 50))),
+    ("negative horizon", dict(horizon=-1)),
+    ("negative cutoff", dict(cutoff=-1e-3)),
+    ("cutoff above density peak", dict(cutoff=10.0)),
+    ("wrong param count", dict(params=(1.0, 2.0))),
+    ("unicycle wrong dims", dict(dyn="unicycle", params=(0.1,))),
+]
+
+
+@pytest.mark.parametrize("what,kw", BAD, ids=[b[0] for b in BAD])
+def test_invalid_problems_are_rejected(A, what, kw):
+    p = W.linear2d().with_(**kw)
+    with pytest.raises(A.AmyError) as e:
+        A.query(p)
+    assert e.value.status == A.binding.E_INVALID
+    assert len(str(e.value)) > 20
+
+
+def test_too_many_states_unsupported(A):
+    p = W.linear2d().with_(count=(50000, 50000))
+    with pytest.raises(A.AmyError) as e:
+        A.query(p)
+    assert e.value.status == A.binding.E_UNSUPPORTED

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Element-by-element at sizes the oracle finishes in seconds (several 64-state
+tiles and a ragged tail); sampled states at the full workload sizes for one
+Bellman step; the FP32 path against the FP64 path and invariants at full
+size over the whole horizon.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import TOL_FP32, TOL_FP64, compare, gpu_solve, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_06191_amd as A
+    A.binding.lib()
+
+
+def _uni_small(**kw):
+    # the unicycle workload's cell widths, noise and cutoff on a smaller domain
+    p = W.unicycle3d(nxy=100, ntheta=60)
+    lo, h, cnt = W.tiling((0.0, 0.0, -math.pi), (2.2, 2.3, math.pi), (22, 23, 60))
+    return p.with_(lo=lo, h=h, count=cnt, target=W.box((1.5, 1.5), (2.2, 2.3), 3),
+                   avoid=W.box((0.6, 0.6), (1.0, 1.2), 3), horizon=kw.pop("horizon", 8),
+                   name="unicycle-patch", **kw)
+
+
+def _room_small(**kw):
+    # the room workload's cell width, noise and cutoff on a 5^5 patch around 20
+    p = W.room5d()
+    lo, h, cnt = W.tiling((19.75,) * 5, (20.25,) * 5, (5,) * 5)
+    return p.with_(lo=lo, h=h, count=cnt, horizon=kw.pop("horizon", 6), name="room-patch", **kw)
+
+
+CASES = {
+    "linear2d-full-fp64-stored": lambda: W.linear2d(precision="fp64", mode="stored"),
+    "linear2d-full-fp64-otf": lambda: W.linear2d(precision="fp64", mode="otf"),
+    "linear2d-full-fp32-otf": lambda: W.linear2d(precision="fp32", mode="otf"),
+    "linear2d-full-fp32-stored": lambda: W.linear2d(precision="fp32", mode="stored"),
+    "unicycle-patch-fp32-otf": lambda: _uni_small(precision="fp32", mode="otf"),
+    "unicycle-patch-fp64-otf": lambda: _uni_small(precision="fp64", mode="otf"),
+    "unicycle-patch-fp32-stored": lambda: _uni_small(precision="fp32", mode="stored"),
+    "unicycle-patch-reach-fp32": lambda: _uni_small(precision="fp32", spec="reach"),
+    "room-patch-fp32-otf": lambda: _room_small(precision="fp32"),
+    "room-patch-fp64-otf": lambda: _room_small(precision="fp64"),
+    "room-patch-fp64-stored": lambda: _room_small(precision="fp64", mode="stored"),
+    "vehicle7-small-fp32": lambda: W.vehicle7d(cells=4, horizon=4).with_(u_count=(3, 3)),
+    "vehicle7-small-fp64": lambda: W.vehicle7d(cells=4, horizon=4, precision="fp64").with_(u_count=(3, 3)),
+    "linear2d-safebox-fp32": lambda: W.linear2d(cells=37, precision="fp32", mode="otf").with_(
+        safe=W.box((-0.8, -0.9), (0.95, 0.7), 2)),
+    "linear2d-nocut-fp64": lambda: W.linear2d(cells=21, precision="fp64", mode="otf").with_(cutoff=0.0),
+    "linear2d-nocut-fp32-stored": lambda: W.linear2d(cells=21, precision="fp32", mode="stored").with_(cutoff=0.0),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity_small(orc, name):
+    p = CASES[name]()
+    say(f"[parity] {name}: n_x={p.n_x} n_u={p.n_u} T_d={p.horizon} {p.precision} {p.mode}")
+    ref = orc.solve(p, gap=True)
+    V, pol, info = gpu_solve(p)
+    tol = TOL_FP64 if p.precision == "fp64" else TOL_FP32
+    err = compare(p, ref, V, pol, tol, gap=ref["gap"])
+    # the FP64 tail bound agrees with the oracle's
+    assert abs(info["max_row_tail"] - ref["max_tail"]) <= 1e-13 + 1e-9 * ref["max_tail"]
+    say(f"[parity] {name}: max err {err:.2e}  tail {info['max_row_tail']:.3e}")
+
+
+EDGE = {
+    "single-partial-tile": lambda: W.linear2d(cells=7, precision="fp64", mode="otf"),
+    "horizon0": lambda: _uni_small(precision="fp32", horizon=0),
+    "horizon1": lambda: _uni_small(precision="fp32", horizon=1),
+    "one-input": lambda: W.linear2d(cells=30, precision="fp32", mode="otf").with_(
+        u_lo=(0.0,), u_hi=(0.0,), u_count=(1,)),
+    "n1": lambda: W.Problem(lo=(-1.0,), h=(2.0 / 301,), count=(301,), u_lo=(-0.3,), u_hi=(0.3,),
+                            u_count=(7,), dyn="affine", params=W.affine_params([[1.01]], [[1.0]]),
+                            var=(0.02 ** 2,), cutoff=1e-3, horizon=10, spec="reach",
+                            target=W.box((0.5,), (0.7,), 1), precision="fp32", mode="otf", name="n1"),
+    "wide-cut-L1": lambda: W.linear2d(cells=8, precision="fp32", mode="otf").with_(cutoff=2.0),
+    "leaves-grid": lambda: W.linear2d(cells=24, precision="fp64", mode="otf").with_(
+        params=W.affine_params([[1.3, 0.0], [0.0, 1.25]], [[0.0], [1.0]], [0.4, -0.3])),
+    "room3-per-room-heaters": lambda: W.room5d(cells=9, n=3, horizon=5, precision="fp32").with_(
+        u_lo=(0.0, 0.0, 0.0), u_hi=(1.0, 1.0, 1.0), u_count=(2, 3, 2)),
+}
+
+
+@pytest.mark.parametrize("name", list(EDGE))
+def test_parity_edge_cases(orc, name):
+    p = EDGE[name]()
+    say(f"[edge] {name}: n_x={p.n_x} n_u={p.n_u} T_d={p.horizon}")
+    ref = orc.solve(p, gap=True)
+    V, pol, _ = gpu_solve(p)
+    tol = TOL_FP64 if p.precision == "fp64" else TOL_FP32
+    compare(p, ref, V, pol, tol, gap=ref["gap"])
+
+
+def test_deterministic_repeat():
+    p = _uni_small(precision="fp32")
+    say("[determinism] two solves bitwise equal")
+    a, pa, _ = gpu_solve(p)
+    b, pb, _ = gpu_solve(p)
+    assert np.array_equal(a, b) and np.array_equal(pa, pb)
+
+
+def test_stored_matches_otf():
+    p = _room_small(precision="fp32", horizon=8)
+    say("[stored vs otf] room patch fp32")
+    a, pa, _ = gpu_solve(p.with_(mode="otf"))
+    b, pb, _ = gpu_solve(p.with_(mode="stored"))
+    assert np.abs(a - b).max() <= 2e-6
+
+
+# ------------------------------------------------------------ full sizes
+
+FULL = {
+    "unicycle-100x100x60": lambda: W.unicycle3d(),
+    "room5-20^5": lambda: W.room5d(),
+    "vehicle7-8^7": lambda: W.vehicle7d(),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_full_size_first_step_sampled(orc, name):
+    """One Bellman step (k = T_d) at full size in the bench's launch shape,
+    checked at sampled states, each computed by the oracle on its own."""
+    p = FULL[name]().with_(horizon=1)
+    say(f"[full-step] {name}: n_x={p.n_x} n_u={p.n_u}")
+    V, pol, _ = gpu_solve(p)
+    rng = np.random.default_rng(11)
+    states = np.unique(np.concatenate([rng.integers(0, p.n_x, 300), [0, p.n_x - 1]]))
+    Vr, pr, gap = orc.step(p, states)
+    err = float(np.abs(V[states] - Vr).max())
+    assert err <= TOL_FP32, f"{name}: {err}"
+    clear = gap > 2 * TOL_FP32
+    assert np.array_equal(pol[0][states][clear], pr[clear])
+    say(f"[full-step] {name}: max err {err:.2e} over {len(states)} states")
+
+
+@pytest.mark.parametrize("name", ["unicycle-100x100x60", "room5-20^5"])
+def test_full_size_fp32_vs_fp64_and_invariants(name):
+    """Whole horizon at full size: FP32 within 1e-5 of the plain FP64 path,
+    values in [0, 1] and monotone in the horizon."""
+    p = FULL[name]()
+    say(f"[full] {name}: fp32 vs fp64, T_d={p.horizon}")
+    v32, _, i32 = gpu_solve(p.with_(precision="fp32"), policy=False)
+    v64, _, i64 = gpu_solve(p.with_(precision="fp64"), policy=False)
+    err = float(np.abs(v32 - v64).max())
+    say(f"[full] {name}: max |fp32 - fp64| = {err:.2e}; sweeps {i32['t_sweeps_ms']:.1f} ms vs "
+        f"{i64['t_sweeps_ms']:.1f} ms")
+    assert err <= TOL_FP32
+    assert v64.min() >= 0.0 and v64.max() <= 1.0 + 1e-12
+    shorter, _, _ = gpu_solve(p.with_(precision="fp64", horizon=p.horizon // 2), policy=False)
+    sign = -1.0 if p.spec == "safety" else 1.0
+    assert np.all(sign * (v64 - shorter) >= -1e-12)
+
+
+def test_full_size_separable_5d(orc):
+    """20^5 grid, diagonal linear dynamics, one input, safety: the 5-D GPU
+    value is the product of five 1-D oracle values."""
+    a = [0.95, 0.9, 1.0, 0.92, 0.97]
+    c = [0.03, -0.02, 0.0, 0.05, -0.01]
+    lo, h, cnt = W.tiling((-1.0,) * 5, (1.0,) * 5, (20,) * 5)
+    var = (0.05 ** 2, 0.04 ** 2, 0.06 ** 2, 0.05 ** 2, 0.03 ** 2)
+    p = W.Problem(lo=lo, h=h, count=cnt, u_lo=(0.0,), u_hi=(0.0,), u_count=(1,), dyn="affine",
+                  params=W.affine_params(np.diag(a), np.zeros((5, 1)), c), var=var, cutoff=1e-5,
+                  horizon=12, spec="safety", precision="fp64", mode="otf", name="separable5")
+    say("[separable] 20^5 product identity")
+    V, _, _ = gpu_solve(p, policy=False)
+    prod = np.ones(1)
+    for i in range(5):
+        p1 = W.Problem(lo=(lo[i],), h=(h[i],), count=(20,), u_lo=(0.0,), u_hi=(0.0,), u_count=(1,),
+                       dyn="affine", params=W.affine_params([[a[i]]], [[0.0]], [c[i]]), var=(var[i],),
+                       cutoff=1e-5, horizon=12, spec="safety")
+        prod = np.multiply.outer(prod, orc.solve(p1)["V"])
+    err = float(np.abs(V - prod.ravel()).max())
+    assert err <= TOL_FP64, err
+    v32, _, _ = gpu_solve(p.with_(precision="fp32"), policy=False)
+    assert float(np.abs(v32 - prod.ravel()).max()) <= TOL_FP32

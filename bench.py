@@ -1,0 +1,197 @@
+"""Benchmark: Bellman (state,input) row-updates per second on one MI355X.
+
+A step is one whole solve of the hot path on one synthetic problem already
+resident on the device: labels, the FP64 cut-off tail pass, T_d Bellman
+sweeps (rows recomputed on the fly) and the FP64 readout.  The default
+workload is the 3-D unicycle reach-avoid problem (100 x 100 x 60 states,
+45 inputs, horizon 16) solved with the FP32 path; the plain FP64 path is
+timed beside it, and the two results are compared.
+
+Prints one JSON line (rank 0).  Usage:
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (packed), published
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64, published
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, published
+C_ERFC = 20                  # flops charged per 1-D erfc evaluation
+
+WORKLOADS = {
+    "unicycle3d": lambda prec, mode: W.unicycle3d(precision=prec, mode=mode),
+    "room5d": lambda prec, mode: W.room5d(precision=prec, mode=mode),
+    "vehicle7d": lambda prec, mode: W.vehicle7d(precision=prec, mode=mode),
+    "linear2d": lambda prec, mode: W.linear2d(precision=prec, mode=mode),
+}
+
+
+def algorithmic_flops_per_row(plan) -> float:
+    """3W + C_erfc * edges: a multiply-add with V per window cell (2 flops),
+    one multiply per cell to form its mass from the 1-D masses, and one
+    erfc per window edge (sum_i (L_i + 1) edges)."""
+    L = [x for x in plan["window"] if x > 0]
+    edges = sum(l + 1 for l in L)
+    return 3.0 * plan["W"] + C_ERFC * edges
+
+
+def stored_bytes_per_row(plan, f64: bool) -> float:
+    """Stored sweep: the row's W masses plus its int32 window origin."""
+    return plan["W"] * (8 if f64 else 4) + 4
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    f, c = math.floor(k), math.ceil(k)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def run_solves(solver, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        solver.solve(policy=True, info=True)
+    torch.cuda.synchronize()
+    lat, main, sweeps, n_main = [], [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = solver.solve(policy=True, info=True)
+        lat.append(r.info["t_total_ms"])
+        main.append(r.info["t_main_sweeps_ms"])
+        sweeps.append(r.info["t_sweeps_ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(wall=wall, lat=lat, main=main, sweeps=sweeps, info=r.info, V=r.V)
+
+
+def cpu_baseline(p, budget_s=15.0):
+    """The FP64 oracle, unchanged, on a bounded sample: one Bellman step
+    (k = T_d) at a strided sample of states, all inputs of each state."""
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if threads <= 0:
+        threads = len(os.sched_getaffinity(0))
+    threads = max(1, min(threads, 16))
+    n_cal = 2000
+    st = np.linspace(0, p.n_x - 1, n_cal).astype(np.int64)
+    t = time.perf_counter()
+    oracle.step(p, st, threads=threads)
+    dt = max(time.perf_counter() - t, 1e-3)
+    n = int(min(p.n_x, max(n_cal, n_cal * budget_s / dt)))
+    st = np.linspace(0, p.n_x - 1, n).astype(np.int64)
+    t = time.perf_counter()
+    oracle.step(p, st, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": n * p.n_u / dt, "unit": "row-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one Bellman step from the terminal values at {n} evenly strided states x "
+                      f"{p.n_u} inputs ({n * p.n_u} row-updates) of the same problem, {dt:.1f} s, "
+                      f"FP64 oracle with {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="otf", choices=["otf", "stored"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the solve is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2005_06191_amd as A
+    torch.cuda.set_device(0)
+
+    p32 = WORKLOADS[args.workload]("fp32", args.mode)
+    s32 = A.Solver(p32)
+    plan = s32.plan
+    rows = p32.rows
+    T = p32.horizon
+    r32 = run_solves(s32, args.steps, args.warmup)
+    ms_per_step = 1e3 * r32["wall"] / args.steps
+    value = rows * T * args.steps / r32["wall"]
+
+    # dominant kernel: the working-precision sweep (T_d - 1 launches per solve)
+    n_main = max(T - 1, 1)
+    sweep_ms = statistics.mean(r32["main"]) / n_main
+    if args.mode == "otf":
+        fl = algorithmic_flops_per_row(plan)
+        achieved = fl * rows / (sweep_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "k_sweep_otf (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
+                "flops_per_row": fl, "rows_per_launch": rows}
+    else:
+        by = stored_bytes_per_row(plan, False)
+        achieved = by * rows / (sweep_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "k_sweep_stored (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
+                "bytes_per_row": by, "rows_per_launch": rows}
+
+    out = {
+        "metric": "Bellman (state,input) row-updates/sec FP32 vs FP64 at <=1e-5 err; p50/p99",
+        "value": value,
+        "unit": "row-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{p32.name} {p32.spec} {args.mode} (n_x={p32.n_x}, n_u={p32.n_u}, "
+                               f"T_d={T}, W={plan['W']})",
+                   "states": p32.n_x, "inputs": p32.n_u, "horizon": T, "rows": rows,
+                   "window": plan["window"][:p32.n], "W": plan["W"], "mode": args.mode},
+        "p50_ms": percentile(r32["lat"], 0.5),
+        "p99_ms": percentile(r32["lat"], 0.99),
+        "tail_bound_E": r32["info"]["tail_bound_E"],
+        "roofline": roof,
+    }
+    if not args.no_fp64:
+        p64 = p32.with_(precision="fp64")
+        s64 = A.Solver(p64)
+        r64 = run_solves(s64, max(3, args.steps // 2), 1)
+        v64 = rows * T * max(3, args.steps // 2) / r64["wall"]
+        err = float((r32["V"] - r64["V"]).abs().max().item())
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["wall"] / max(3, args.steps // 2),
+                       "p50_ms": percentile(r64["lat"], 0.5), "p99_ms": percentile(r64["lat"], 0.99)}
+        out["speedup_fp32_vs_fp64"] = value / v64
+        out["max_abs_err_fp32_vs_fp64"] = err
+        out["err_tol"] = 1e-5
+        out["err_ok"] = bool(err <= 1e-5)
+        del s64
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p32.with_(precision="fp64"))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,7 +150,11 @@ typedef struct {
   uint64_t stored_bytes;         /* of which transition rows (STORED mode)   */
   double max_row_tail;           /* max over rows of the cut-off mass (FP64) */
   double tail_bound_E;           /* T_d * max_row_tail: V_{no cut} <= V + E  */
-  double t_build_ms, t_sweeps_ms, t_readout_ms, t_total_ms;
+  /* phase times (HIP events on the solve's stream), filled when info != NULL:
+   * build = labels, tail and (STORED) row construction; sweeps = all T_d
+   * Bellman steps; main_sweeps = the first T_d - 1 of them (the steps that
+   * read and write the working precision; the last step writes FP64 V). */
+  double t_build_ms, t_sweeps_ms, t_main_sweeps_ms, t_readout_ms, t_total_ms;
 } amy_info;
 
 /* Validate p and fill sizes, the mode AUTO resolves to for a workspace of

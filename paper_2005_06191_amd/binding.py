@@ -57,7 +57,8 @@ class Info(C.Structure):
                 ("workspace_bytes", C.c_uint64), ("stored_bytes", C.c_uint64),
                 ("max_row_tail", C.c_double), ("tail_bound_E", C.c_double),
                 ("t_build_ms", C.c_double), ("t_sweeps_ms", C.c_double),
-                ("t_readout_ms", C.c_double), ("t_total_ms", C.c_double)]
+                ("t_main_sweeps_ms", C.c_double), ("t_readout_ms", C.c_double),
+                ("t_total_ms", C.c_double)]
 
     def as_dict(self):
         d = {}

@@ -264,6 +264,7 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
   int cur = 0;
   for (int k = horizon; k >= 1; --k) {
     const bool last = (k == 1);
+    if (tm && last) hipEventRecord(tm->ev[2], st);
     const SweepKind sk = pl.f64 ? SWEEP_F64 : (last ? SWEEP_F32_LAST : SWEEP_F32);
     void* out = last ? (void*)V_out : Vb[cur ^ 1];
     int16_t* pk = pol ? pol + (int64_t)(k - 1) * D.n_x : nullptr;
@@ -276,8 +277,9 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
     cur ^= 1;
   }
   if (tm) {
-    hipEventRecord(tm->ev[2], st);
+    if (horizon == 0) hipEventRecord(tm->ev[2], st);
     hipEventRecord(tm->ev[3], st);
+    hipEventRecord(tm->ev[4], st);
   }
   return AMY_OK;
 }
@@ -295,7 +297,7 @@ extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* worksp
   Timing tm;
   Timing* tp = nullptr;
   if (info) {
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < Timing::N; ++i) {
       hipError_t e = hipEventCreate(&tm.ev[i]);
       if (e != hipSuccess) return amy_hip_fail(e, "hipEventCreate");
     }
@@ -303,7 +305,7 @@ extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* worksp
   }
   st = amy_enqueue(pl, hs, workspace, V_out, policy_out, p->horizon, info != nullptr, tp);
   if (st == AMY_OK && info) {
-    hipError_t e = hipEventSynchronize(tm.ev[3]);
+    hipError_t e = hipEventSynchronize(tm.ev[4]);
     if (e != hipSuccess) st = amy_hip_fail(e, "solve");
     else {
       fill_info(p, pl, info);
@@ -317,15 +319,17 @@ extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* worksp
       float ms;
       hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]);
       info->t_build_ms = ms;
-      hipEventElapsedTime(&ms, tm.ev[1], tm.ev[2]);
+      hipEventElapsedTime(&ms, tm.ev[1], tm.ev[3]);
       info->t_sweeps_ms = ms;
-      hipEventElapsedTime(&ms, tm.ev[2], tm.ev[3]);
+      hipEventElapsedTime(&ms, tm.ev[1], tm.ev[2]);
+      info->t_main_sweeps_ms = ms;
+      hipEventElapsedTime(&ms, tm.ev[3], tm.ev[4]);
       info->t_readout_ms = ms;
-      hipEventElapsedTime(&ms, tm.ev[0], tm.ev[3]);
+      hipEventElapsedTime(&ms, tm.ev[0], tm.ev[4]);
       info->t_total_ms = ms;
     }
   }
   if (tp)
-    for (int i = 0; i < 4; ++i) hipEventDestroy(tm.ev[i]);
+    for (int i = 0; i < Timing::N; ++i) hipEventDestroy(tm.ev[i]);
   return st;
 }

@@ -16,8 +16,11 @@ struct Plan {
   uint64_t stored_bytes, ws_bytes;
 };
 
+// ev[0] start, ev[1] sweeps begin, ev[2] after the first T_d - 1 sweeps,
+// ev[3] after the last sweep, ev[4] end.
 struct Timing {
-  hipEvent_t ev[4];
+  static const int N = 5;
+  hipEvent_t ev[N];
 };
 
 amy_status amy_fail(amy_status st, const char* fmt, ...);

@@ -88,6 +88,13 @@ typedef enum { AMY_FP64 = 0, AMY_FP32 = 1 } amy_precision;
  *                    Sec. 8.3 with its printed right-hand sides, saturations
  *                    = clamps to the input box; params = {tau, l_wb, m, mu_bar,
  *                    l_f, l_r, h_cg, I_z, C_Sf, C_Sr, g}. */
+/* Bellman-sweep kernel variant.  AUTO lets the library (and its autotuner
+ * cache) choose; the others force one, for tests and tuning:
+ *   LANES  one lane per state, window lengths at run time (any shape);
+ *   FIXED  one lane per state, window shape compiled in (the instantiated
+ *          shapes of the built-in workload families only). */
+typedef enum { AMY_VARIANT_AUTO = 0, AMY_VARIANT_LANES = 1, AMY_VARIANT_FIXED = 2 } amy_variant;
+
 typedef enum {
   AMY_DYN_AFFINE = 0,
   AMY_DYN_UNICYCLE = 1,
@@ -139,12 +146,17 @@ typedef struct {
   amy_box safe;                  /* safety                                   */
   int32_t mode;                  /* amy_mode                                 */
   int32_t precision;             /* amy_precision                            */
+  int32_t variant;               /* amy_variant (0 = AUTO)                   */
 } amy_problem;
 
 typedef struct {
   int32_t mode_used;             /* AMY_MODE_STORED or AMY_MODE_OTF          */
   int32_t window[AMY_MAX_DIM];   /* L_i                                      */
-  int32_t kernel;                /* sweep variant: lanes per row (1 or 64)   */
+  int32_t kernel;                /* amy_variant the sweeps ran with          */
+  int32_t table_cache_mask;      /* bit i: dimension i's 1-D tables are built
+                                    once per state for every input-digit
+                                    combination its mean depends on          */
+  int32_t lds_bytes;             /* dynamic LDS per 64-state workgroup       */
   int64_t n_x, n_u, rows, W;     /* states, inputs, rows = n_x n_u, slots    */
   uint64_t workspace_bytes;      /* bytes amy_solve needs for this problem   */
   uint64_t stored_bytes;         /* of which transition rows (STORED mode)   */

@@ -23,6 +23,8 @@ SPEC = {"safety": 0, "reach": 1, "reach_avoid": 2}
 MODE = {"auto": 0, "stored": 1, "otf": 2}
 MODE_NAME = {v: k for k, v in MODE.items()}
 PREC = {"fp64": 0, "fp32": 1}
+VARIANT = {"auto": 0, "lanes": 1, "fixed": 2}
+VARIANT_NAME = {v: k for k, v in VARIANT.items()}
 
 
 class Grid(C.Structure):
@@ -48,11 +50,12 @@ class ProblemC(C.Structure):
                 ("noise_var", C.c_double * MAX_DIM), ("cutoff", C.c_double),
                 ("horizon", C.c_int32), ("spec", C.c_int32),
                 ("target", Box), ("avoid", Box), ("safe", Box),
-                ("mode", C.c_int32), ("precision", C.c_int32)]
+                ("mode", C.c_int32), ("precision", C.c_int32), ("variant", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("mode_used", C.c_int32), ("window", C.c_int32 * MAX_DIM), ("kernel", C.c_int32),
+                ("table_cache_mask", C.c_int32), ("lds_bytes", C.c_int32),
                 ("n_x", C.c_int64), ("n_u", C.c_int64), ("rows", C.c_int64), ("W", C.c_int64),
                 ("workspace_bytes", C.c_uint64), ("stored_bytes", C.c_uint64),
                 ("max_row_tail", C.c_double), ("tail_bound_E", C.c_double),
@@ -68,6 +71,7 @@ class Info(C.Structure):
                 v = [int(x) for x in v]
             d[name] = v
         d["mode"] = MODE_NAME.get(self.mode_used, "?")
+        d["variant"] = VARIANT_NAME.get(self.kernel, "?")
         return d
 
 
@@ -115,7 +119,7 @@ def _box(dst, b, n, empty_default):
         dst.lo[i], dst.hi[i] = lo, hi
 
 
-def to_struct(p, mode=None, precision=None) -> ProblemC:
+def to_struct(p, mode=None, precision=None, variant=None) -> ProblemC:
     """Marshal a problem description (any object with the fields of
     workloads.Problem) into the C struct."""
     s = ProblemC()
@@ -139,6 +143,7 @@ def to_struct(p, mode=None, precision=None) -> ProblemC:
     _box(s.safe, p.safe, n, False)
     s.mode = MODE[mode or p.mode]
     s.precision = PREC[precision or p.precision]
+    s.variant = VARIANT[variant or getattr(p, "variant", "auto")]
     return s
 
 
@@ -189,6 +194,7 @@ class Solver:
 
 
 def solve(p, policy: bool = True, info: bool = True, budget: int = 0, **kw) -> Result:
+    """One solve; keyword overrides: mode=, precision=, variant=."""
     return Solver(p, budget=budget, **kw).solve(policy=policy, info=info)
 
 

@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libamytiss_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["amy_kernels.hip", "amy_host.cpp"]
+SOURCES = ["amy_kernels.hip", "amy_gen_affine.hip", "amy_gen_room.hip", "amy_gen_misc.hip",
+           "amy_fixed.hip", "amy_host.cpp"]
 
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -198,7 +198,8 @@ struct Dyn<AMY_DYN_VEHICLE7_, 7> {
 
 // Kept cells of dimension i for mean mu: [jlo, b-1] (empty when b == jlo),
 // and the origin o of the fixed L_i-slot window, o <= jlo, o + L_i <= n_i.
-struct Win { int jlo, b, o; };
+// z0 = (lo - mu) / sigma is the edge coordinate of grid edge 0.
+struct Win { int jlo, b, o; double z0; };
 
 __device__ __forceinline__ Win window_1d(const DevProblem& P, int i, double mu) {
   const int n = P.count[i], L = P.L[i];
@@ -208,8 +209,9 @@ __device__ __forceinline__ Win window_1d(const DevProblem& P, int i, double mu) 
     w.b = n;
   } else {
     // cell j is kept iff its centre lo + (j + 1/2) h lies in [mu - x*, mu + x*]
-    double tl = ((mu - P.xstar[i]) - P.lo[i]) * P.inv_h[i] - 0.5;
-    double th = ((mu + P.xstar[i]) - P.lo[i]) * P.inv_h[i] - 0.5;
+    const double m = mu * P.inv_h[i];
+    double tl = m - P.win_a[i];
+    double th = m - P.win_b[i];
     tl = fmin(fmax(tl, -1.0), (double)n);
     th = fmin(fmax(th, -2.0), (double)n);
     const int jlo = max(0, (int)ceil(tl));
@@ -219,6 +221,7 @@ __device__ __forceinline__ Win window_1d(const DevProblem& P, int i, double mu) 
     w.b = max(jhi + 1, jlo);
   }
   w.o = min(w.jlo, n - L);
+  w.z0 = (P.lo[i] - mu) * P.inv_sigma[i];
   return w;
 }
 
@@ -226,7 +229,9 @@ __device__ __forceinline__ float ec_of(double z, float) {
   return erfcf((float)(fabs(z) * 0.70710678118654752440));
 }
 __device__ __forceinline__ double ec_of(double z, double) {
-  return erfc(fabs(z) * 0.70710678118654752440);
+  const double a = fabs(z);
+  // erfc(a / sqrt 2) underflows to 0 in FP64 beyond a ~ 38.6
+  return a > 38.5 ? 0.0 : erfc(a * 0.70710678118654752440);
 }
 
 // Phi(z1) - Phi(z0) from e = erfc(|z|/sqrt 2): upper-tail difference when
@@ -239,47 +244,74 @@ __device__ __forceinline__ MT mass_of(double z0, MT e0, double z1, MT e1) {
   return MT(1) - MT(0.5) * (e0 + e1);
 }
 
-__device__ __forceinline__ double edge_z(const DevProblem& P, int i, int E, double mu) {
-  return ((P.lo[i] + (double)E * P.h[i]) - mu) * P.inv_sigma[i];
+__device__ __forceinline__ double edge_z(const DevProblem& P, int i, const Win& w, int E) {
+  return w.z0 + (double)E * P.hs[i];
 }
 
-// 1-D masses of the L_i window slots of dimension i into t[k*ts]; returns o.
+// 1-D masses of the L_i window slots of dimension i into t[k*ts] (slot k is
+// cell o + k; cells outside the kept range get mass 0 because their two
+// edges are clamped onto the same kept-range edge).
 template <class MT>
-__device__ __forceinline__ int dim_table(const DevProblem& P, int i, double mu, MT* t, int ts) {
+__device__ __forceinline__ Win dim_table(const DevProblem& P, int i, double mu, MT* t, int ts) {
   const Win w = window_1d(P, i, mu);
   const int L = P.L[i];
-  double zp = edge_z(P, i, min(max(w.o, w.jlo), w.b), mu);
+  double zp = edge_z(P, i, w, min(max(w.o, w.jlo), w.b));
   MT ep = ec_of(zp, MT());
   for (int k = 0; k < L; ++k) {
-    const double z = edge_z(P, i, min(max(w.o + k + 1, w.jlo), w.b), mu);
+    const double z = edge_z(P, i, w, min(max(w.o + k + 1, w.jlo), w.b));
     const MT e = ec_of(z, MT());
     t[k * ts] = mass_of(zp, ep, z, e);
     zp = z;
     ep = e;
   }
-  return w.o;
+  return w;
 }
 
 // FP64 mass of [edge ea, edge eb] of dimension i.
-__device__ __forceinline__ double mass_edges(const DevProblem& P, int i, int ea, int eb, double mu) {
-  const double za = edge_z(P, i, ea, mu), zb = edge_z(P, i, eb, mu);
+__device__ __forceinline__ double mass_edges(const DevProblem& P, int i, const Win& w, int ea, int eb) {
+  const double za = edge_z(P, i, w, ea), zb = edge_z(P, i, w, eb);
   return mass_of(za, ec_of(za, 0.0), zb, ec_of(zb, 0.0));
+}
+
+// FP64 kept-window mass and grid mass of dimension i (the per-row tail is
+// prod_i grid_i - prod_i win_i).
+__device__ __forceinline__ void win_grid_mass(const DevProblem& P, int i, const Win& w, double& win,
+                                              double& grid) {
+  win = mass_edges(P, i, w, w.jlo, w.b);
+  grid = mass_edges(P, i, w, 0, P.count[i]);
+}
+
+// Input digits of table c of dimension i (digits the mean does not depend on are 0).
+__device__ __forceinline__ void combo_digits(const DevProblem& P, int i, int c, InputWalk& iw) {
+#pragma unroll
+  for (int k = 0; k < AMY_MAXI; ++k) {
+    const int mlt = P.dep_mult[i][k];
+    iw.dig[k] = (k < P.m && mlt > 0) ? (c / mlt) % P.ucount[k] : 0;
+  }
+}
+
+__device__ __forceinline__ int combo_index(const DevProblem& P, int i, const InputWalk& iw) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < AMY_MAXI; ++k) c += iw.dig[k] * P.dep_mult[i][k];
+  return c;
 }
 
 // ------------------------------------------------------------- contraction
 
 // sum over the window of prod_i t_i[k_i] * V[base + sum_i k_i stride_i],
-// innermost dimension first.  COMP: Kahan-compensated outermost sum.
+// innermost dimension first; t_i starts at table entry toff[i].
+// COMP: Kahan-compensated outermost sum.
 template <int D, int N, class MT, class AT, class VT, bool COMP>
 __device__ __forceinline__ AT contract(const DevProblem& P, const MT* __restrict__ t, int ts,
-                                       const VT* __restrict__ V, int64_t base) {
+                                       const int* toff, const VT* __restrict__ V, int64_t base) {
   const int L = P.L[D];
-  const MT* td = t + P.Loff[D] * ts;
+  const MT* td = t + toff[D] * ts;
   AT acc = AT(0), c = AT(0);
   for (int k = 0; k < L; ++k) {
     AT inner;
     if constexpr (D == N - 1) inner = AT(V[base + k]);
-    else inner = contract<D + 1, N, MT, AT, VT, COMP>(P, t, ts, V, base + (int64_t)k * P.stride[D]);
+    else inner = contract<D + 1, N, MT, AT, VT, COMP>(P, t, ts, toff, V, base + (int64_t)k * P.stride[D]);
     if constexpr (COMP && D == 0) {
       const AT y = AT(td[k * ts]) * inner - c;
       const AT s2 = acc + y;
@@ -291,3 +323,94 @@ __device__ __forceinline__ AT contract(const DevProblem& P, const MT* __restrict
   }
   return acc;
 }
+
+// ---------------------------------------------------------------- row engine
+
+// Per-lane LDS views of one 64-lane block: 1-D tables [entry][lane], cached
+// window origins [slot][lane], and (tail pass) FP64 window / grid masses of
+// the cached tables [2 slot + {0,1}][lane].
+template <class MT>
+struct LaneLds {
+  MT* tab;
+  int32_t* org;
+  double* wg;
+  __device__ __forceinline__ LaneLds(const DevProblem& P, unsigned char* smem, int lane) {
+    tab = reinterpret_cast<MT*>(smem) + lane;
+    org = reinterpret_cast<int32_t*>(smem + P.lds_int_off) + lane;
+    wg = reinterpret_cast<double*>(smem + P.lds_tail_off) + lane;
+  }
+};
+
+// Build every cached table of state x (all input-digit combinations of the
+// dimensions whose tables are cached).
+template <int KIND, int N, class MT, bool TAIL, int LB>
+__device__ __forceinline__ void build_cached(const DevProblem& P, const typename Dyn<KIND, N>::State& st,
+                                             const double* x, const LaneLds<MT>& S) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int C = P.ccount[i];
+    for (int c = 0; c < C; ++c) {
+      InputWalk iw;
+      combo_digits(P, i, c, iw);
+      double uv[AMY_MAXI], mu[N];
+      iw.values(P, uv);
+      Dyn<KIND, N>::apply(P, st, x, uv, mu);
+      const Win w = dim_table<MT>(P, i, mu[i], S.tab + (P.toff[i] + c * P.L[i]) * LB, LB);
+      S.org[(P.ooff[i] + c) * LB] = w.o;
+      if constexpr (TAIL) {
+        double wm, gm;
+        win_grid_mass(P, i, w, wm, gm);
+        S.wg[(2 * (P.ooff[i] + c)) * LB] = wm;
+        S.wg[(2 * (P.ooff[i] + c) + 1) * LB] = gm;
+      }
+    }
+  }
+}
+
+// Tables of the current input: table offsets toff[] and window base index;
+// rebuilds uncached tables whose mean changed.  TAIL: returns the row's
+// FP64 tail (grid mass - kept-window mass).
+template <int KIND, int N, class MT, bool TAIL, int LB>
+struct RowState {
+  double prev[N];
+  int o[N];
+  double wmem[TAIL ? N : 1], gmem[TAIL ? N : 1];
+  __device__ __forceinline__ void reset() {
+#pragma unroll
+    for (int i = 0; i < N; ++i) prev[i] = __builtin_nan("");
+  }
+  __device__ __forceinline__ int64_t prepare(const DevProblem& P, const InputWalk& iw, const double* mu,
+                                             const LaneLds<MT>& S, int* toff, double& tail) {
+    int64_t base = 0;
+    double win = 1.0, grid = 1.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      int oi;
+      if (P.ccount[i] > 0) {
+        const int c = combo_index(P, i, iw);
+        toff[i] = P.toff[i] + c * P.L[i];
+        oi = S.org[(P.ooff[i] + c) * LB];
+        if constexpr (TAIL) {
+          win *= S.wg[(2 * (P.ooff[i] + c)) * LB];
+          grid *= S.wg[(2 * (P.ooff[i] + c) + 1) * LB];
+        }
+      } else {
+        if (mu[i] != prev[i]) {
+          const Win w = dim_table<MT>(P, i, mu[i], S.tab + P.toff[i] * LB, LB);
+          o[i] = w.o;
+          prev[i] = mu[i];
+          if constexpr (TAIL) win_grid_mass(P, i, w, wmem[i], gmem[i]);
+        }
+        toff[i] = P.toff[i];
+        oi = o[i];
+        if constexpr (TAIL) {
+          win *= wmem[i];
+          grid *= gmem[i];
+        }
+      }
+      base += (int64_t)oi * P.stride[i];
+    }
+    if constexpr (TAIL) tail = grid - win;
+    return base;
+  }
+};

@@ -1,0 +1,48 @@
+// amy_gen_room.hip -- generic-window kernels of the room dynamics family.
+#include "amy_generic.hpp"
+
+hipError_t amy_gen_room_tail(const DevProblem& P, const uint8_t* label, unsigned long long* tailmax,
+                              hipStream_t st) {
+  switch (P.n) {
+    case 1: return Launch<AMY_DYN_ROOM_, 1>::tail(P, label, tailmax, st);
+    case 2: return Launch<AMY_DYN_ROOM_, 2>::tail(P, label, tailmax, st);
+    case 3: return Launch<AMY_DYN_ROOM_, 3>::tail(P, label, tailmax, st);
+    case 4: return Launch<AMY_DYN_ROOM_, 4>::tail(P, label, tailmax, st);
+    case 5: return Launch<AMY_DYN_ROOM_, 5>::tail(P, label, tailmax, st);
+    case 6: return Launch<AMY_DYN_ROOM_, 6>::tail(P, label, tailmax, st);
+    case 7: return Launch<AMY_DYN_ROOM_, 7>::tail(P, label, tailmax, st);
+    case 8: return Launch<AMY_DYN_ROOM_, 8>::tail(P, label, tailmax, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t amy_gen_room_sweep(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                               const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                               hipStream_t st) {
+  switch (P.n) {
+    case 1: return Launch<AMY_DYN_ROOM_, 1>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 2: return Launch<AMY_DYN_ROOM_, 2>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 3: return Launch<AMY_DYN_ROOM_, 3>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 4: return Launch<AMY_DYN_ROOM_, 4>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 5: return Launch<AMY_DYN_ROOM_, 5>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 6: return Launch<AMY_DYN_ROOM_, 6>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 7: return Launch<AMY_DYN_ROOM_, 7>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 8: return Launch<AMY_DYN_ROOM_, 8>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t amy_gen_room_build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,
+                               unsigned long long* tailmax, hipStream_t st) {
+  switch (P.n) {
+    case 1: return Launch<AMY_DYN_ROOM_, 1>::build(P, f64, label, T, org, tailmax, st);
+    case 2: return Launch<AMY_DYN_ROOM_, 2>::build(P, f64, label, T, org, tailmax, st);
+    case 3: return Launch<AMY_DYN_ROOM_, 3>::build(P, f64, label, T, org, tailmax, st);
+    case 4: return Launch<AMY_DYN_ROOM_, 4>::build(P, f64, label, T, org, tailmax, st);
+    case 5: return Launch<AMY_DYN_ROOM_, 5>::build(P, f64, label, T, org, tailmax, st);
+    case 6: return Launch<AMY_DYN_ROOM_, 6>::build(P, f64, label, T, org, tailmax, st);
+    case 7: return Launch<AMY_DYN_ROOM_, 7>::build(P, f64, label, T, org, tailmax, st);
+    case 8: return Launch<AMY_DYN_ROOM_, 8>::build(P, f64, label, T, org, tailmax, st);
+  }
+  return hipErrorInvalidValue;
+}

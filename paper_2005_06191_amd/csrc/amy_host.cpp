@@ -92,6 +92,7 @@ amy_status amy_validate(const amy_problem* p) {
   if (p->spec < AMY_SAFETY || p->spec > AMY_REACH_AVOID) return amy_fail(AMY_E_INVALID, "bad spec");
   if (p->mode < AMY_MODE_AUTO || p->mode > AMY_MODE_OTF) return amy_fail(AMY_E_INVALID, "bad mode");
   if (p->precision != AMY_FP64 && p->precision != AMY_FP32) return amy_fail(AMY_E_INVALID, "bad precision");
+  if (p->variant < AMY_VARIANT_AUTO || p->variant > AMY_VARIANT_FIXED) return amy_fail(AMY_E_INVALID, "bad variant");
   const int ep = expected_params(p);
   if (ep < 0) return amy_fail(AMY_E_INVALID, "bad dynamics kind %d", p->dyn.kind);
   if (p->dyn.kind == AMY_DYN_UNICYCLE && (n != 3 || m != 2))
@@ -104,6 +105,132 @@ amy_status amy_validate(const amy_problem* p) {
     return amy_fail(AMY_E_INVALID, "dynamics needs %d params, got %d", ep, p->dyn.n_params);
   for (int k = 0; k < p->dyn.n_params; ++k)
     if (!isfinite(p->dyn.params[k])) return amy_fail(AMY_E_INVALID, "param %d not finite", k);
+  return AMY_OK;
+}
+
+// Input dimensions each state dimension's mean depends on (bit k = input
+// dimension k), from the structure of each dynamics family.
+static uint32_t dep_mask(const amy_problem* p, int i) {
+  const int n = p->grid.n, m = p->inputs.m;
+  uint32_t all = (1u << m) - 1u;
+  switch (p->dyn.kind) {
+    case AMY_DYN_AFFINE: {
+      uint32_t d = 0;
+      for (int k = 0; k < m; ++k)
+        if (p->dyn.params[n * n + i * m + k] != 0.0) d |= 1u << k;
+      return d;
+    }
+    case AMY_DYN_UNICYCLE: return i < 2 ? 1u : 2u;  // x, y: speed; theta: turn rate
+    case AMY_DYN_ROOM: return m == 1 ? 1u : (1u << i);
+    case AMY_DYN_VEHICLE7: {
+      // mu_3 <- v1; mu_4, mu_7 <- v2; mu_6 <- v1, v2 (either branch); others none
+      static const uint32_t d[7] = {0u, 0u, 1u, 2u, 0u, 3u, 2u};
+      return d[i];
+    }
+  }
+  return all;
+}
+
+static const int LDS_BUDGET = 64 * 1024;  // bytes of dynamic LDS per 64-lane block
+
+// Which dimensions get all their tables built once per state (the others
+// are rebuilt in the input loop when their mean changes), and the LDS layout.
+static amy_status plan_tables(const amy_problem* p, Plan* pl) {
+  DevProblem& D = pl->dev;
+  const int n = D.n, m = D.m;
+  const int msz = pl->f64 ? 8 : 4;
+  int runs[AMY_MAX_DIM], C[AMY_MAX_DIM];
+  uint32_t dep[AMY_MAX_DIM];
+  for (int i = 0; i < n; ++i) {
+    dep[i] = dep_mask(p, i);
+    C[i] = 1;
+    int kmax = -1;
+    for (int k = 0; k < m; ++k)
+      if (dep[i] >> k & 1u) {
+        C[i] *= D.ucount[k];
+        kmax = k;
+      }
+    // consecutive-input runs of an unchanged mean in the natural input order
+    runs[i] = 1;
+    for (int k = 0; k <= kmax; ++k) runs[i] *= D.ucount[k];
+    D.ccount[i] = 0;
+  }
+  auto bytes = [&](bool tail) {
+    int64_t ent = 0, slots = 0;
+    for (int i = 0; i < n; ++i) {
+      ent += (D.ccount[i] > 0) ? (int64_t)D.ccount[i] * D.L[i] : D.L[i];
+      if (D.ccount[i] > 0) slots += D.ccount[i];
+    }
+    // regions plus their alignment padding (at most one table row + 32 B)
+    int64_t b = ent * msz * 64 + slots * 4 * 64 + msz * 64 + 32;
+    if (tail) b += slots * 2 * 8 * 64;
+    return b;
+  };
+  if (bytes(true) > LDS_BUDGET)
+    return amy_fail(AMY_E_UNSUPPORTED, "window tables need %lld B of LDS per 64 lanes (> %d)",
+                    (long long)bytes(true), LDS_BUDGET);
+  // greedy: cache the dimension saving the most edge evaluations per byte
+  for (;;) {
+    int best = -1;
+    double best_gain = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (D.ccount[i] > 0 || C[i] >= runs[i]) continue;
+      D.ccount[i] = C[i];
+      const int64_t b = bytes(true);
+      D.ccount[i] = 0;
+      if (b > LDS_BUDGET) continue;
+      const double gain = (double)(runs[i] - C[i]) * (D.L[i] + 1) / (double)(C[i] * D.L[i] + 1);
+      if (gain > best_gain) {
+        best_gain = gain;
+        best = i;
+      }
+    }
+    if (best < 0) break;
+    D.ccount[best] = C[best];
+  }
+  // LDS layout of a 64-lane block (each region [entry][lane]):
+  //   cached tables | cached origins | uncached tables | FP64 tail masses
+  // The compiled-shape sweep keeps uncached tables in registers and
+  // allocates only the first two regions (plus the last on the tail pass).
+  int64_t ent_c = 0, ent_u = 0, slots = 0;
+  for (int i = 0; i < n; ++i) {
+    if (D.ccount[i] > 0) {
+      ent_c += (int64_t)D.ccount[i] * D.L[i];
+      slots += D.ccount[i];
+    } else {
+      ent_u += D.L[i];
+    }
+  }
+  const int64_t row = (int64_t)msz * 64;   // bytes per table entry across the block
+  D.lds_int_off = (int32_t)(((ent_c * row + 15) / 16) * 16);
+  const int64_t unc_off = D.lds_int_off + ((slots * 4 * 64 + 15) / 16) * 16;
+  const int64_t unc_entry0 = (unc_off + row - 1) / row;
+  D.lds_tail_off = (int32_t)((((unc_entry0 + ent_u) * row) + 15) / 16 * 16);
+  D.lds_bytes = D.lds_tail_off;
+  D.lds_bytes_tail = D.lds_tail_off + (int32_t)(slots * 2 * 8 * 64);
+  D.lds_bytes_fixed = (int32_t)unc_off;
+  int64_t ec = 0, eu = unc_entry0, sl = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < AMY_MAXI; ++k) D.dep_mult[i][k] = 0;
+    D.ooff[i] = (int32_t)sl;
+    if (D.ccount[i] > 0) {
+      D.toff[i] = (int32_t)ec;
+      ec += (int64_t)D.ccount[i] * D.L[i];
+      sl += D.ccount[i];
+      int mult = 1;
+      for (int k = m - 1; k >= 0; --k)
+        if (dep[i] >> k & 1u) {
+          D.dep_mult[i][k] = mult;
+          mult *= D.ucount[k];
+        }
+    } else {
+      D.toff[i] = (int32_t)eu;
+      eu += D.L[i];
+    }
+  }
+  if (D.lds_bytes_tail > LDS_BUDGET)
+    return amy_fail(AMY_E_UNSUPPORTED, "window tables need %d B of LDS per 64 lanes (> %d)", D.lds_bytes_tail,
+                    LDS_BUDGET);
   return AMY_OK;
 }
 
@@ -123,7 +250,6 @@ void amy_make_plan(const amy_problem* p, Plan* pl) {
   }
   D.n_x = (int32_t)nx;
   int64_t W = 1;
-  int off = 0;
   for (int i = 0; i < n; ++i) {
     D.count[i] = p->grid.count[i];
     D.lo[i] = p->grid.lo[i];
@@ -131,20 +257,20 @@ void amy_make_plan(const amy_problem* p, Plan* pl) {
     D.inv_h[i] = 1.0 / p->grid.h[i];
     const double sigma = sqrt(p->noise_var[i]);
     D.inv_sigma[i] = 1.0 / sigma;
+    D.hs[i] = p->grid.h[i] * D.inv_sigma[i];
     int L = p->grid.count[i];
     if (!D.nocut) {
       D.xstar[i] = xstar_of(p->noise_var[i], p->cutoff);
       const double l = floor(2.0 * D.xstar[i] / p->grid.h[i]) + 1.0;
       if (l < (double)L) L = (int)l;
+      D.win_a[i] = (D.xstar[i] + D.lo[i]) * D.inv_h[i] + 0.5;
+      D.win_b[i] = (D.lo[i] - D.xstar[i]) * D.inv_h[i] + 0.5;
     } else {
       D.xstar[i] = INFINITY;
     }
     D.L[i] = L;
-    D.Loff[i] = off;
-    off += L;
     W *= L;
   }
-  D.Loff[n] = off;
   D.W = (int32_t)(W < 2147483647 ? W : 2147483647);
   int nu = 1;
   for (int k = 0; k < m; ++k) {
@@ -209,10 +335,13 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   if (budget && pl->ws_bytes > budget)
     return amy_fail(AMY_E_NOMEM, "workspace %llu B exceeds budget %llu B",
                     (unsigned long long)pl->ws_bytes, (unsigned long long)budget);
-  // the lane kernel keeps each lane's 1-D tables in LDS
-  if (amy_lane_lds_bytes(pl->dev, pl->f64) > 64 * 1024)
-    return amy_fail(AMY_E_UNSUPPORTED, "window tables need %zu B of LDS (> 64 KiB)",
-                    amy_lane_lds_bytes(pl->dev, pl->f64));
+  amy_status st = plan_tables(p, pl);
+  if (st != AMY_OK) return st;
+  // sweep variant: the compiled-shape kernel where one exists, unless forced
+  const bool fixed_ok = amy_fixed_available(pl->dev);
+  if (p->variant == AMY_VARIANT_FIXED && !fixed_ok)
+    return amy_fail(AMY_E_UNSUPPORTED, "no compiled kernel for this window shape");
+  pl->dev.variant = (p->variant == AMY_VARIANT_LANES || !fixed_ok) ? AMY_VARIANT_LANES : AMY_VARIANT_FIXED;
   return AMY_OK;
 }
 
@@ -220,7 +349,11 @@ static void fill_info(const amy_problem* p, const Plan& pl, amy_info* info) {
   memset(info, 0, sizeof *info);
   info->mode_used = pl.mode;
   for (int i = 0; i < p->grid.n; ++i) info->window[i] = pl.dev.L[i];
-  info->kernel = 1;
+  info->kernel = pl.dev.variant;
+  info->table_cache_mask = 0;
+  for (int i = 0; i < p->grid.n; ++i)
+    if (pl.dev.ccount[i] > 0) info->table_cache_mask |= 1 << i;
+  info->lds_bytes = pl.dev.lds_bytes;
   info->n_x = pl.dev.n_x;
   info->n_u = pl.dev.n_u;
   info->rows = pl.rows;
@@ -252,12 +385,14 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
   if (tm) hipEventRecord(tm->ev[0], st);
   if ((e = amy_launch_init(D, label, Vb[0], pl.f64, horizon == 0 ? V_out : nullptr, tailmax, st)) != hipSuccess)
     return amy_hip_fail(e, "init kernel");
-  if (want_tail && (e = amy_launch_tail(D, label, tailmax, st)) != hipSuccess)
+  // the FP64 tail pass rides on the first kernel that builds every row
+  // (the stored-mode build, else the first sweep); alone only when T_d = 0
+  if (want_tail && horizon == 0 && (e = amy_launch_tail(D, label, tailmax, st)) != hipSuccess)
     return amy_hip_fail(e, "tail kernel");
   const bool stored = (pl.mode == AMY_MODE_STORED);
   if (stored && horizon > 0) {
-    if ((e = amy_launch_build(D, pl.f64, label, base + pl.off_T, (int32_t*)(base + pl.off_org), st)) !=
-        hipSuccess)
+    if ((e = amy_launch_build(D, pl.f64, label, base + pl.off_T, (int32_t*)(base + pl.off_org),
+                              want_tail ? tailmax : nullptr, st)) != hipSuccess)
       return amy_hip_fail(e, "build kernel");
   }
   if (tm) hipEventRecord(tm->ev[1], st);
@@ -271,8 +406,12 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
     if (stored)
       e = amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
                                   label, pk, st);
+    else if (D.variant == AMY_VARIANT_FIXED)
+      e = amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk,
+                                 (want_tail && k == horizon) ? tailmax : nullptr, st);
     else
-      e = amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk, st);
+      e = amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk,
+                               (want_tail && k == horizon) ? tailmax : nullptr, st);
     if (e != hipSuccess) return amy_hip_fail(e, "sweep kernel");
     cur ^= 1;
   }

@@ -1,428 +1,50 @@
-// amy_kernels.hip -- gfx950 kernels of the abstraction + Bellman hot path.
-//
-// Launch shape shared by the row kernels: one lane per state, 64 states per
-// workgroup (one wave), workgroups renumbered XCD-contiguously.  A lane walks
-// all inputs of its state (Alg. 4's parallel loop over X x U, with the loop
-// over U kept inside the lane so that the max / argmax over inputs of
-// Alg. 4's collect step is a running register max: no second kernel, no
-// cross-lane reduction, no V_in buffer).  The per-dimension 1-D mass tables
-// of the lane's current row sit in LDS ([table entry][lane], conflict-free);
-// a table is rebuilt only when its dimension's mean changes between
-// consecutive inputs (for the unicycle the x and y tables depend on v only).
-//
-// Kernels:
-//   k_init        labels (free / fixed 0 / fixed 1) and the terminal value
-//   k_tail        FP64 per-row cut-off tail, max over rows (bound E)
-//   k_sweep_otf   one Bellman step with rows recomputed on the fly (Sec. 6.1)
-//   k_build       stored mode: rows of T written once (Alg. 2)
-//   k_sweep_stored one Bellman step streaming the stored rows
-//   k_copy_out    terminal vector to the FP64 output (T_d = 0)
-#include <hip/hip_runtime.h>
+// amy_kernels.hip -- dispatch of the generic-window kernels by dynamics
+// family, and the family-independent kernels (init, copy, stored sweep).
+#include "amy_generic.hpp"
 
-#include "amy_device.hpp"
-#include "amy_kernels.hpp"
+#define DECL_FAMILY(name)                                                                                \
+  hipError_t amy_gen_##name##_tail(const DevProblem&, const uint8_t*, unsigned long long*, hipStream_t); \
+  hipError_t amy_gen_##name##_sweep(const DevProblem&, SweepKind, const void*, void*, const uint8_t*,   \
+                                    int16_t*, unsigned long long*, hipStream_t);                         \
+  hipError_t amy_gen_##name##_build(const DevProblem&, bool, const uint8_t*, void*, int32_t*,           \
+                                    unsigned long long*, hipStream_t);
+DECL_FAMILY(affine)
+DECL_FAMILY(room)
+DECL_FAMILY(unicycle)
+DECL_FAMILY(vehicle7)
 
-#define LANE_BLOCK 64
-
-// ------------------------------------------------------------------ init
-
-template <class VT>
-__global__ void __launch_bounds__(256) k_init(DevProblem P, uint8_t* __restrict__ label,
-                                              VT* __restrict__ V0, double* __restrict__ Vout,
-                                              unsigned long long* __restrict__ tailmax) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0 && tailmax) *tailmax = 0ull;
-  if (s >= P.n_x) return;
-  double x[AMY_MAXD];
-  uint32_t r = (uint32_t)s;
-#pragma unroll
-  for (int i = AMY_MAXD - 1; i >= 0; --i) {
-    if (i < P.n) {
-      const uint32_t c = (uint32_t)P.count[i];
-      const uint32_t q = r / c;
-      x[i] = P.lo[i] + ((double)(r - q * c) + 0.5) * P.h[i];
-      r = q;
-    }
-  }
-  bool in_t = true, in_a = true, in_s = true;
-#pragma unroll
-  for (int i = 0; i < AMY_MAXD; ++i) {
-    if (i < P.n) {
-      in_t = in_t && (x[i] >= P.tlo[i] && x[i] <= P.thi[i]);
-      in_a = in_a && (x[i] >= P.alo[i] && x[i] <= P.ahi[i]);
-      in_s = in_s && (x[i] >= P.slo[i] && x[i] <= P.shi[i]);
-    }
-  }
-  uint8_t lb;
-  double v;
-  if (P.spec == 0) {
-    lb = in_s ? LBL_FREE : LBL_ZERO;
-    v = in_s ? 1.0 : 0.0;
-  } else if (P.spec == 2 && in_a) {
-    lb = LBL_ZERO;
-    v = 0.0;
-  } else if (in_t) {
-    lb = LBL_ONE;
-    v = 1.0;
-  } else {
-    lb = LBL_FREE;
-    v = 0.0;
-  }
-  label[s] = lb;
-  V0[s] = (VT)v;
-  if (Vout) Vout[s] = v;
-}
-
-// ------------------------------------------------------------------ tail
-
-// max over rows (x free, all u) of  P_mu(grid box) - P_mu(kept window), FP64.
-template <int KIND, int N>
-__global__ void __launch_bounds__(LANE_BLOCK) k_tail(DevProblem P, const uint8_t* __restrict__ label,
-                                                     unsigned long long* __restrict__ tailmax) {
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
-  double tmax = 0.0;
-  if (s < (uint32_t)P.n_x && label[s] == LBL_FREE) {
-    double x[N];
-    state_centre<N>(P, s, x);
-    typename Dyn<KIND, N>::State st;
-    Dyn<KIND, N>::prep(P, x, st);
-    InputWalk iw;
-    iw.reset();
-    for (int u = 0; u < P.n_u; ++u) {
-      double uv[AMY_MAXI], mu[N];
-      iw.values(P, uv);
-      Dyn<KIND, N>::apply(P, st, x, uv, mu);
-      double grid = 1.0, win = 1.0;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const Win w = window_1d(P, i, mu[i]);
-        grid *= mass_edges(P, i, 0, P.count[i], mu[i]);
-        win *= mass_edges(P, i, w.jlo, w.b, mu[i]);
-      }
-      tmax = fmax(tmax, grid - win);
-      iw.next(P);
-    }
-  }
-  // wave max, then one atomic per wave (non-negative doubles order as their bits)
-  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-  if (threadIdx.x == 0 && tmax > 0.0)
-    atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
-}
-
-// ------------------------------------------------------------- OTF sweep
-
-// One Bellman step k: Vout[x] = max_u sum_window T(.|x,u) Vin, policy = argmax.
-// Vin / Vout hold extended values (1 on T\A, 0 on A and outside S), so the
-// reach / reach-avoid T0 term of Alg. 4 is the window mass on target cells.
-template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP>
-__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_otf(DevProblem P, const VI* __restrict__ Vin,
-                                                          VO* __restrict__ Vout,
-                                                          const uint8_t* __restrict__ label,
-                                                          int16_t* __restrict__ pol) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  MT* tab = reinterpret_cast<MT*>(smem) + threadIdx.x;
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
-  if (s >= (uint32_t)P.n_x) return;
-  const uint8_t lb = label[s];
-  if (lb != LBL_FREE) {
-    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
-    if (pol) pol[s] = -1;
-    return;
-  }
-  double x[N];
-  state_centre<N>(P, s, x);
-  typename Dyn<KIND, N>::State st;
-  Dyn<KIND, N>::prep(P, x, st);
-  double prev[N];
-  int o[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) prev[i] = __builtin_nan("");
-  InputWalk iw;
-  iw.reset();
-  AT best = AT(-1);
-  int arg = 0;
-  for (int u = 0; u < P.n_u; ++u) {
-    double uv[AMY_MAXI], mu[N];
-    iw.values(P, uv);
-    Dyn<KIND, N>::apply(P, st, x, uv, mu);
-    int64_t base = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      if (mu[i] != prev[i]) {
-        o[i] = dim_table<MT>(P, i, mu[i], tab + P.Loff[i] * LANE_BLOCK, LANE_BLOCK);
-        prev[i] = mu[i];
-      }
-      base += (int64_t)o[i] * P.stride[i];
-    }
-    const AT q = contract<0, N, MT, AT, VI, COMP>(P, tab, LANE_BLOCK, Vin, base);
-    if (q > best) {
-      best = q;
-      arg = u;
-    }
-    iw.next(P);
-  }
-  Vout[s] = VO(best);
-  if (pol) pol[s] = (int16_t)arg;
-}
-
-// --------------------------------------------------------------- stored
-
-// Stored row layout: rows grouped by 64-state tiles; within a tile, input u
-// and slot w, the 64 states are contiguous:
-//   T[((tile * n_u + u) * W + w) * 64 + lane],  org[(tile * n_u + u) * 64 + lane].
-template <int D, int N, class MT>
-__device__ __forceinline__ void write_row(const DevProblem& P, const MT* __restrict__ t, MT pre,
-                                          MT* __restrict__& out) {
-  const MT* td = t + P.Loff[D] * LANE_BLOCK;
-  for (int k = 0; k < P.L[D]; ++k) {
-    const MT p = (D == 0) ? td[k * LANE_BLOCK] : pre * td[k * LANE_BLOCK];
-    if constexpr (D == N - 1) {
-      *out = p;
-      out += LANE_BLOCK;
-    } else {
-      write_row<D + 1, N, MT>(P, t, p, out);
-    }
-  }
-}
-
-template <int KIND, int N, class MT>
-__global__ void __launch_bounds__(LANE_BLOCK) k_build(DevProblem P, const uint8_t* __restrict__ label,
-                                                      MT* __restrict__ T, int32_t* __restrict__ org) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  MT* tab = reinterpret_cast<MT*>(smem) + threadIdx.x;
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
-  if (s >= (uint32_t)P.n_x || label[s] != LBL_FREE) return;
-  double x[N];
-  state_centre<N>(P, s, x);
-  typename Dyn<KIND, N>::State st;
-  Dyn<KIND, N>::prep(P, x, st);
-  double prev[N];
-  int o[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) prev[i] = __builtin_nan("");
-  InputWalk iw;
-  iw.reset();
-  const int64_t tile = s / LANE_BLOCK, lane = s % LANE_BLOCK;
-  for (int u = 0; u < P.n_u; ++u) {
-    double uv[AMY_MAXI], mu[N];
-    iw.values(P, uv);
-    Dyn<KIND, N>::apply(P, st, x, uv, mu);
-    int64_t base = 0;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      if (mu[i] != prev[i]) {
-        o[i] = dim_table<MT>(P, i, mu[i], tab + P.Loff[i] * LANE_BLOCK, LANE_BLOCK);
-        prev[i] = mu[i];
-      }
-      base += (int64_t)o[i] * P.stride[i];
-    }
-    const int64_t rt = tile * P.n_u + u;
-    MT* out = T + rt * (int64_t)P.W * LANE_BLOCK + lane;
-    write_row<0, N, MT>(P, tab, MT(1), out);
-    org[rt * LANE_BLOCK + lane] = (int32_t)base;
-    iw.next(P);
-  }
-}
-
-template <int D, int N, class MT, class AT, class VT, bool COMP>
-__device__ __forceinline__ void stored_sum(const DevProblem& P, const MT* __restrict__& t,
-                                           const VT* __restrict__ V, int64_t base, AT& acc, AT& c) {
-  for (int k = 0; k < P.L[D]; ++k) {
-    if constexpr (D == N - 1) {
-      const AT term = AT(*t) * AT(V[base + k]);
-      t += LANE_BLOCK;
-      if constexpr (COMP) {
-        const AT y = term - c;
-        const AT s2 = acc + y;
-        c = (s2 - acc) - y;
-        acc = s2;
-      } else {
-        acc = acc + term;
-      }
-    } else {
-      stored_sum<D + 1, N, MT, AT, VT, COMP>(P, t, V, base + (int64_t)k * P.stride[D], acc, c);
-    }
-  }
-}
-
-template <int N, class MT, class AT, class VI, class VO, bool COMP>
-__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_stored(DevProblem P, const MT* __restrict__ T,
-                                                             const int32_t* __restrict__ org,
-                                                             const VI* __restrict__ Vin,
-                                                             VO* __restrict__ Vout,
-                                                             const uint8_t* __restrict__ label,
-                                                             int16_t* __restrict__ pol) {
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
-  if (s >= (uint32_t)P.n_x) return;
-  const uint8_t lb = label[s];
-  if (lb != LBL_FREE) {
-    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
-    if (pol) pol[s] = -1;
-    return;
-  }
-  const int64_t tile = s / LANE_BLOCK, lane = s % LANE_BLOCK;
-  AT best = AT(-1);
-  int arg = 0;
-  for (int u = 0; u < P.n_u; ++u) {
-    const int64_t rt = tile * P.n_u + u;
-    const MT* t = T + rt * (int64_t)P.W * LANE_BLOCK + lane;
-    const int64_t base = org[rt * LANE_BLOCK + lane];
-    AT acc = AT(0), c = AT(0);
-    stored_sum<0, N, MT, AT, VI, COMP>(P, t, Vin, base, acc, c);
-    if (acc > best) {
-      best = acc;
-      arg = u;
-    }
-  }
-  Vout[s] = VO(best);
-  if (pol) pol[s] = (int16_t)arg;
-}
-
-template <class VT>
-__global__ void __launch_bounds__(256) k_copy_out(int64_t n, const VT* __restrict__ src,
-                                                  double* __restrict__ dst) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < n) dst[s] = (double)src[s];
-}
-
-// ============================================================ host launchers
-
-static inline unsigned lane_grid(int64_t n_x) { return (unsigned)((n_x + LANE_BLOCK - 1) / LANE_BLOCK); }
-
-template <class MT>
-static inline size_t tab_bytes(const DevProblem& P) {
-  return (size_t)P.Loff[P.n] * LANE_BLOCK * sizeof(MT);
-}
+#define AMY_DISPATCH(OP, ...)                                                \
+  switch (P.kind) {                                                           \
+    case AMY_DYN_AFFINE_: return amy_gen_affine_##OP(__VA_ARGS__);           \
+    case AMY_DYN_ROOM_: return amy_gen_room_##OP(__VA_ARGS__);               \
+    case AMY_DYN_UNICYCLE_: return amy_gen_unicycle_##OP(__VA_ARGS__);       \
+    case AMY_DYN_VEHICLE7_: return amy_gen_vehicle7_##OP(__VA_ARGS__);       \
+  }                                                                           \
+  return hipErrorInvalidValue;
 
 hipError_t amy_launch_init(const DevProblem& P, uint8_t* label, void* V0, bool v0_double, double* Vout,
                            unsigned long long* tailmax, hipStream_t st) {
-  const unsigned g = (unsigned)((P.n_x + 255) / 256);
-  if (v0_double)
-    hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(256), 0, st, P, label, (double*)V0, Vout, tailmax);
-  else
-    hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, st, P, label, (float*)V0, Vout, tailmax);
-  return hipGetLastError();
+  return amy_launch_init_impl(P, label, V0, v0_double, Vout, tailmax, st);
 }
 
 hipError_t amy_launch_copy_out(int64_t n, const void* src, bool src_double, double* dst, hipStream_t st) {
-  const unsigned g = (unsigned)((n + 255) / 256);
-  if (src_double)
-    hipLaunchKernelGGL(k_copy_out<double>, dim3(g), dim3(256), 0, st, n, (const double*)src, dst);
-  else
-    hipLaunchKernelGGL(k_copy_out<float>, dim3(g), dim3(256), 0, st, n, (const float*)src, dst);
-  return hipGetLastError();
+  return amy_launch_copy_out_impl(n, src, src_double, dst, st);
 }
-
-template <int KIND, int N>
-struct Launch {
-  static hipError_t tail(const DevProblem& P, const uint8_t* label, unsigned long long* tailmax,
-                         hipStream_t st) {
-    hipLaunchKernelGGL((k_tail<KIND, N>), dim3(lane_grid(P.n_x)), dim3(LANE_BLOCK), 0, st, P, label,
-                       tailmax);
-    return hipGetLastError();
-  }
-  static hipError_t sweep(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
-                          const uint8_t* label, int16_t* pol, hipStream_t st) {
-    const dim3 g(lane_grid(P.n_x)), b(LANE_BLOCK);
-    switch (sk) {
-      case SWEEP_F64:
-        hipLaunchKernelGGL((k_sweep_otf<KIND, N, double, double, double, double, false>), g, b,
-                           tab_bytes<double>(P), st, P, (const double*)Vin, (double*)Vout, label, pol);
-        break;
-      case SWEEP_F32:
-        hipLaunchKernelGGL((k_sweep_otf<KIND, N, float, float, float, float, true>), g, b,
-                           tab_bytes<float>(P), st, P, (const float*)Vin, (float*)Vout, label, pol);
-        break;
-      case SWEEP_F32_LAST:
-        hipLaunchKernelGGL((k_sweep_otf<KIND, N, float, double, float, double, false>), g, b,
-                           tab_bytes<float>(P), st, P, (const float*)Vin, (double*)Vout, label, pol);
-        break;
-    }
-    return hipGetLastError();
-  }
-  static hipError_t build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,
-                          hipStream_t st) {
-    const dim3 g(lane_grid(P.n_x)), b(LANE_BLOCK);
-    if (f64)
-      hipLaunchKernelGGL((k_build<KIND, N, double>), g, b, tab_bytes<double>(P), st, P, label,
-                         (double*)T, org);
-    else
-      hipLaunchKernelGGL((k_build<KIND, N, float>), g, b, tab_bytes<float>(P), st, P, label,
-                         (float*)T, org);
-    return hipGetLastError();
-  }
-};
-
-template <int N>
-static hipError_t sweep_stored_n(const DevProblem& P, SweepKind sk, const void* T, const int32_t* org,
-                                 const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
-                                 hipStream_t st) {
-  const dim3 g(lane_grid(P.n_x)), b(LANE_BLOCK);
-  switch (sk) {
-    case SWEEP_F64:
-      hipLaunchKernelGGL((k_sweep_stored<N, double, double, double, double, false>), g, b, 0, st, P,
-                         (const double*)T, org, (const double*)Vin, (double*)Vout, label, pol);
-      break;
-    case SWEEP_F32:
-      hipLaunchKernelGGL((k_sweep_stored<N, float, float, float, float, true>), g, b, 0, st, P,
-                         (const float*)T, org, (const float*)Vin, (float*)Vout, label, pol);
-      break;
-    case SWEEP_F32_LAST:
-      hipLaunchKernelGGL((k_sweep_stored<N, float, double, float, double, false>), g, b, 0, st, P,
-                         (const float*)T, org, (const float*)Vin, (double*)Vout, label, pol);
-      break;
-  }
-  return hipGetLastError();
-}
-
-#define AMY_DISPATCH(KIND_, N_, CALL)                                 \
-  switch (KIND_) {                                                    \
-    case AMY_DYN_AFFINE_:                                             \
-      switch (N_) {                                                   \
-        case 1: return Launch<AMY_DYN_AFFINE_, 1>::CALL;              \
-        case 2: return Launch<AMY_DYN_AFFINE_, 2>::CALL;              \
-        case 3: return Launch<AMY_DYN_AFFINE_, 3>::CALL;              \
-        case 4: return Launch<AMY_DYN_AFFINE_, 4>::CALL;              \
-        case 5: return Launch<AMY_DYN_AFFINE_, 5>::CALL;              \
-        case 6: return Launch<AMY_DYN_AFFINE_, 6>::CALL;              \
-        case 7: return Launch<AMY_DYN_AFFINE_, 7>::CALL;              \
-        case 8: return Launch<AMY_DYN_AFFINE_, 8>::CALL;              \
-      }                                                               \
-      break;                                                          \
-    case AMY_DYN_ROOM_:                                               \
-      switch (N_) {                                                   \
-        case 1: return Launch<AMY_DYN_ROOM_, 1>::CALL;                \
-        case 2: return Launch<AMY_DYN_ROOM_, 2>::CALL;                \
-        case 3: return Launch<AMY_DYN_ROOM_, 3>::CALL;                \
-        case 4: return Launch<AMY_DYN_ROOM_, 4>::CALL;                \
-        case 5: return Launch<AMY_DYN_ROOM_, 5>::CALL;                \
-        case 6: return Launch<AMY_DYN_ROOM_, 6>::CALL;                \
-        case 7: return Launch<AMY_DYN_ROOM_, 7>::CALL;                \
-        case 8: return Launch<AMY_DYN_ROOM_, 8>::CALL;                \
-      }                                                               \
-      break;                                                          \
-    case AMY_DYN_UNICYCLE_:                                           \
-      if (N_ == 3) return Launch<AMY_DYN_UNICYCLE_, 3>::CALL;         \
-      break;                                                          \
-    case AMY_DYN_VEHICLE7_:                                           \
-      if (N_ == 7) return Launch<AMY_DYN_VEHICLE7_, 7>::CALL;         \
-      break;                                                          \
-  }                                                                   \
-  return hipErrorInvalidValue;
 
 hipError_t amy_launch_tail(const DevProblem& P, const uint8_t* label, unsigned long long* tailmax,
                            hipStream_t st) {
-  AMY_DISPATCH(P.kind, P.n, tail(P, label, tailmax, st))
+  AMY_DISPATCH(tail, P, label, tailmax, st)
 }
 
 hipError_t amy_launch_sweep_otf(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
-                                const uint8_t* label, int16_t* pol, hipStream_t st) {
-  AMY_DISPATCH(P.kind, P.n, sweep(P, sk, Vin, Vout, label, pol, st))
+                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                hipStream_t st) {
+  AMY_DISPATCH(sweep, P, sk, Vin, Vout, label, pol, tailmax, st)
 }
 
 hipError_t amy_launch_build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,
-                            hipStream_t st) {
-  AMY_DISPATCH(P.kind, P.n, build(P, f64, label, T, org, st))
+                            unsigned long long* tailmax, hipStream_t st) {
+  AMY_DISPATCH(build, P, f64, label, T, org, tailmax, st)
 }
 
 hipError_t amy_launch_sweep_stored(const DevProblem& P, SweepKind sk, const void* T, const int32_t* org,
@@ -439,8 +61,4 @@ hipError_t amy_launch_sweep_stored(const DevProblem& P, SweepKind sk, const void
     case 8: return sweep_stored_n<8>(P, sk, T, org, Vin, Vout, label, pol, st);
   }
   return hipErrorInvalidValue;
-}
-
-size_t amy_lane_lds_bytes(const DevProblem& P, bool f64) {
-  return f64 ? tab_bytes<double>(P) : tab_bytes<float>(P);
 }

@@ -17,11 +17,19 @@ hipError_t amy_launch_init(const DevProblem& P, uint8_t* label, void* V0, bool v
 hipError_t amy_launch_copy_out(int64_t n, const void* src, bool src_double, double* dst, hipStream_t st);
 hipError_t amy_launch_tail(const DevProblem& P, const uint8_t* label, unsigned long long* tailmax,
                            hipStream_t st);
+// tailmax != NULL: the launch also computes the FP64 max row tail (first step).
 hipError_t amy_launch_sweep_otf(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
-                                const uint8_t* label, int16_t* pol, hipStream_t st);
+                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                hipStream_t st);
 hipError_t amy_launch_build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,
-                            hipStream_t st);
+                            unsigned long long* tailmax, hipStream_t st);
 hipError_t amy_launch_sweep_stored(const DevProblem& P, SweepKind sk, const void* T, const int32_t* org,
                                    const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
                                    hipStream_t st);
-size_t amy_lane_lds_bytes(const DevProblem& P, bool f64);
+
+// Fixed-window-shape sweep (amy_fixed.hip): available for the instantiated
+// window shapes only.
+bool amy_fixed_available(const DevProblem& P);
+hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                                  const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                  hipStream_t st);

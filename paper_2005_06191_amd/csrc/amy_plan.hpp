@@ -17,15 +17,34 @@ struct DevProblem {
   int32_t n, m, kind, spec;
   int32_t count[AMY_MAXD];
   int32_t L[AMY_MAXD];        // fixed window length per dimension
-  int32_t Loff[AMY_MAXD + 1]; // offsets of the per-dimension 1-D tables
   int32_t ucount[AMY_MAXI];
   int32_t n_u;
   int32_t W;                  // prod L
   int32_t nocut;              // cutoff == 0: the window is the whole grid
   int32_t n_x;                // states (< 2^31)
+  // Table caching.  Dimension i's mean depends only on the input dimensions
+  // k with dep_mult[i][k] > 0; its 1-D table for input digits d is table
+  // number c = sum_k d_k dep_mult[i][k] of that dimension.  ccount[i] > 0:
+  // all ccount[i] tables of the state are built once before the input loop;
+  // ccount[i] == 0: the table is rebuilt inside the loop when mu_i changes.
+  int32_t dep_mult[AMY_MAXD][AMY_MAXI];
+  int32_t ccount[AMY_MAXD];
+  int32_t toff[AMY_MAXD];     // first LDS table entry of dimension i
+  int32_t ooff[AMY_MAXD];     // first cached-origin slot of dimension i
+  int32_t lds_int_off;        // byte offset of the origin slots in a block's LDS
+  int32_t lds_tail_off;       // byte offset of the FP64 (window, grid) masses
+  int32_t lds_bytes;          // generic sweep: block LDS without / with the tail region
+  int32_t lds_bytes_tail;
+  int32_t lds_bytes_fixed;    // compiled-shape sweep without the tail region
+  int32_t variant;            // resolved amy_variant of the OTF sweeps
   int64_t stride[AMY_MAXD];   // state index strides, last dimension fastest
   double lo[AMY_MAXD], h[AMY_MAXD], inv_h[AMY_MAXD];
   double inv_sigma[AMY_MAXD], xstar[AMY_MAXD];
+  // window rule precomputed per dimension: kept cells are
+  // ceil(mu inv_h - win_a) .. floor(mu inv_h - win_b), with
+  // win_a = (x* + lo) inv_h + 1/2 and win_b = (lo - x*) inv_h + 1/2;
+  // edge j sits at z = (lo - mu) inv_sigma + j hs, hs = h inv_sigma.
+  double win_a[AMY_MAXD], win_b[AMY_MAXD], hs[AMY_MAXD];
   double ulo[AMY_MAXI], ustep[AMY_MAXI], uhi[AMY_MAXI];
   double tlo[AMY_MAXD], thi[AMY_MAXD];
   double alo[AMY_MAXD], ahi[AMY_MAXD];

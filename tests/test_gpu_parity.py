@@ -185,3 +185,29 @@ def test_full_size_separable_5d(orc):
     assert err <= TOL_FP64, err
     v32, _, _ = gpu_solve(p.with_(precision="fp32"), policy=False)
     assert float(np.abs(v32 - prod.ravel()).max()) <= TOL_FP32
+
+
+@pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "room-patch-fp32-otf",
+                                  "linear2d-full-fp32-otf", "room-patch-fp64-otf"])
+def test_fixed_shape_kernel_matches_generic(name):
+    """The compiled-window-shape sweep does the generic sweep's arithmetic in
+    the same order: results are bitwise equal."""
+    import paper_2005_06191_amd as A
+    p = CASES[name]().with_(horizon=4)
+    assert A.query(p)["variant"] == "fixed"
+    say(f"[fixed vs lanes] {name}")
+    a = A.solve(p, variant="fixed")
+    b = A.solve(p, variant="lanes")
+    assert a.info["variant"] == "fixed" and b.info["variant"] == "lanes"
+    assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())
+    assert np.array_equal(a.policy.cpu().numpy(), b.policy.cpu().numpy())
+    assert a.info["max_row_tail"] == b.info["max_row_tail"]
+
+
+def test_vehicle7_full_fixed_vs_generic_first_step():
+    import paper_2005_06191_amd as A
+    p = W.vehicle7d().with_(horizon=2)
+    say("[fixed vs lanes] vehicle7 full, T_d=2")
+    a = A.solve(p, variant="fixed", policy=False)
+    b = A.solve(p, variant="lanes", policy=False)
+    assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())

@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="otf", choices=["otf", "stored"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "lanes", "fixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     args = ap.parse_args()
@@ -127,7 +128,7 @@ def main():
     torch.cuda.set_device(0)
 
     p32 = WORKLOADS[args.workload]("fp32", args.mode)
-    s32 = A.Solver(p32)
+    s32 = A.Solver(p32, variant=args.variant)
     plan = s32.plan
     rows = p32.rows
     T = p32.horizon
@@ -169,7 +170,8 @@ def main():
         "config": {"workload": f"{p32.name} {p32.spec} {args.mode} (n_x={p32.n_x}, n_u={p32.n_u}, "
                                f"T_d={T}, W={plan['W']})",
                    "states": p32.n_x, "inputs": p32.n_u, "horizon": T, "rows": rows,
-                   "window": plan["window"][:p32.n], "W": plan["W"], "mode": args.mode},
+                   "window": plan["window"][:p32.n], "W": plan["W"], "mode": args.mode,
+                   "variant": plan["variant"]},
         "p50_ms": percentile(r32["lat"], 0.5),
         "p99_ms": percentile(r32["lat"], 0.99),
         "tail_bound_E": r32["info"]["tail_bound_E"],
@@ -177,7 +179,7 @@ def main():
     }
     if not args.no_fp64:
         p64 = p32.with_(precision="fp64")
-        s64 = A.Solver(p64)
+        s64 = A.Solver(p64, variant=args.variant)
         r64 = run_solves(s64, max(3, args.steps // 2), 1)
         v64 = rows * T * max(3, args.steps // 2) / r64["wall"]
         err = float((r32["V"] - r64["V"]).abs().max().item())

@@ -105,12 +105,60 @@ def cpu_baseline(p, budget_s=15.0):
                       f"FP64 oracle with {threads} OpenMP threads"}
 
 
+def bench_batch(args):
+    """The 64-system batch in one persistent launch (FP32); value counts
+    every system's rows x horizon."""
+    import torch
+
+    import paper_2005_06191_amd as A
+    torch.cuda.set_device(0)
+    ps = W.batch_systems()
+    bs = A.BatchSolver(ps)
+    tuned = None
+    if args.tune:
+        tuned = bs.tune()
+    for _ in range(args.warmup):
+        bs.solve(info=True)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = bs.solve(info=True)
+        lat.append(res[0].info["t_total_ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    work = sum(p.rows * p.horizon for p in ps)
+    flops = 0.0
+    for p, r in zip(ps, res):
+        L = [x for x in r.info["window"] if x > 0]
+        flops += p.rows * p.horizon * (3.0 * r.info["W"] + C_ERFC * sum(l + 1 for l in L))
+    kms = statistics.mean(lat)
+    achieved = flops / (kms * 1e-3) / 1e12
+    variants = {}
+    for r in res:
+        variants[r.info["variant"]] = variants.get(r.info["variant"], 0) + 1
+    out = {
+        "metric": "Bellman (state,input) row-updates/sec FP32 vs FP64 at <=1e-5 err; p50/p99",
+        "value": work * args.steps / wall, "unit": "row-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch of {len(ps)} systems (2-D linear / 3-D unicycle), one persistent launch",
+                   "systems": len(ps), "row_updates": work, "variants": variants, "tuned": tuned},
+        "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_batch_persistent (FP32)", "kernel_avg_ms": round(kms, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS) + ["batch64"])
+    ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--mode", default="otf", choices=["otf", "stored"])
     ap.add_argument("--variant", default="auto", choices=["auto", "lanes", "fixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -121,7 +169,10 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
+
     import torch
 
     import paper_2005_06191_amd as A

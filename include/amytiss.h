@@ -90,10 +90,21 @@ typedef enum { AMY_FP64 = 0, AMY_FP32 = 1 } amy_precision;
  *                    l_f, l_r, h_cg, I_z, C_Sf, C_Sr, g}. */
 /* Bellman-sweep kernel variant.  AUTO lets the library (and its autotuner
  * cache) choose; the others force one, for tests and tuning:
- *   LANES  one lane per state, window lengths at run time (any shape);
- *   FIXED  one lane per state, window shape compiled in (the instantiated
- *          shapes of the built-in workload families only). */
-typedef enum { AMY_VARIANT_AUTO = 0, AMY_VARIANT_LANES = 1, AMY_VARIANT_FIXED = 2 } amy_variant;
+ *   LANES    one lane per state, window lengths at run time (any shape whose
+ *            per-lane 1-D tables fit in LDS);
+ *   FIXED    one lane per state, window shape compiled in (the instantiated
+ *            shapes of the built-in workload families only);
+ *   GROUP16  16 lanes per state (4 states per wave) share the state's tables
+ *            and split its window -- for windows of hundreds to thousands
+ *            of cells;
+ *   GROUP64  one wavefront per (state, input) row -- the largest windows. */
+typedef enum {
+  AMY_VARIANT_AUTO = 0,
+  AMY_VARIANT_LANES = 1,
+  AMY_VARIANT_FIXED = 2,
+  AMY_VARIANT_GROUP16 = 3,
+  AMY_VARIANT_GROUP64 = 4
+} amy_variant;
 
 typedef enum {
   AMY_DYN_AFFINE = 0,
@@ -185,6 +196,51 @@ amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_info* out);
  * and the phase times (HIP events on `stream`). */
 amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
                      double* V_out, int16_t* policy_out, amy_info* info);
+
+/* ---------------------------------------------------------------- batch
+ * Many independent systems (uneven grids, inputs and horizons) in ONE
+ * cooperative persistent launch (the batched form of Alg. 4): workgroups
+ * take 64-state tiles from per-XCD work queues, a grid-wide barrier
+ * separates the Bellman steps, and each system's rows are computed exactly
+ * as amy_solve computes them with AMY_VARIANT_LANES (bitwise equal).
+ * All systems share one precision and run on the fly (mode AUTO or OTF);
+ * the compiled families are affine n = 1..4, unicycle, room n = 2..5 and
+ * the 7-D vehicle.  Horizons up to 1024, up to 4096 systems. */
+
+/* Workspace bytes of a batch (no device work). */
+amy_status amy_batch_query(const amy_problem* probs, int32_t count, uint64_t* ws_bytes);
+
+/* Solve count systems.  V_out[i]: device double[n_x(i)]; policy_out: NULL
+ * or count device int16 buffers (each T_d(i) * n_x(i), entries may be NULL).
+ * infos: NULL (asynchronous) or count amy_info, filled after waiting for the
+ * stream (including each system's FP64 tail bound; t_total_ms is the time
+ * of the whole launch).  AMY_E_DEVICE if a grid-barrier wait gave up. */
+amy_status amy_batch_solve(const amy_problem* probs, int32_t count, void* stream, void* workspace,
+                           uint64_t ws_bytes, double* const* V_out, int16_t* const* policy_out,
+                           amy_info* infos);
+
+/* --------------------------------------------------------------- autotuner
+ * Measures candidate launch configurations on the device and caches the
+ * fastest per shape class (dynamics, dimension, window, precision, size
+ * buckets); later calls with mode/variant AUTO use the cached choice.
+ * Single solve: sweep variant.  Batch: tiles per work-queue grab, resident
+ * workgroups per CU, XCD-partitioned queues.  Tuning overwrites V_out. */
+typedef struct {
+  int32_t chunk, blocks_per_cu, xcd_order, variant;
+  int32_t candidates;
+  double best_ms, worst_ms;
+} amy_tune_result;
+
+amy_status amy_tune_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
+                          double* V_out, amy_tune_result* out);
+amy_status amy_tune_batch(const amy_problem* probs, int32_t count, void* stream, void* workspace,
+                          uint64_t ws_bytes, double* const* V_out, amy_tune_result* out);
+/* The cache as JSON {"<shape class>": {"chunk":..,"blocks_per_cu":..,"xcd_order":..,
+ * "variant":..,"ms":..}}; load merges into the in-process cache. */
+amy_status amy_tune_save(const char* path);
+amy_status amy_tune_load(const char* path);
+amy_status amy_tune_clear(void);
+int32_t amy_tune_entries(void);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* amy_last_error(void);

@@ -23,7 +23,7 @@ SPEC = {"safety": 0, "reach": 1, "reach_avoid": 2}
 MODE = {"auto": 0, "stored": 1, "otf": 2}
 MODE_NAME = {v: k for k, v in MODE.items()}
 PREC = {"fp64": 0, "fp32": 1}
-VARIANT = {"auto": 0, "lanes": 1, "fixed": 2}
+VARIANT = {"auto": 0, "lanes": 1, "fixed": 2, "group16": 3, "group64": 4}
 VARIANT_NAME = {v: k for k, v in VARIANT.items()}
 
 
@@ -75,6 +75,15 @@ class Info(C.Structure):
         return d
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("blocks_per_cu", C.c_int32), ("xcd_order", C.c_int32),
+                ("variant", C.c_int32), ("candidates", C.c_int32), ("best_ms", C.c_double),
+                ("worst_ms", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class AmyError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"amytiss {STATUS.get(status, status)}: {msg}")
@@ -97,6 +106,22 @@ def lib():
         L.amy_query.restype = C.c_int
         L.amy_solve.argtypes = [pp, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, ip]
         L.amy_solve.restype = C.c_int
+        L.amy_batch_query.argtypes = [pp, C.c_int32, C.POINTER(C.c_uint64)]
+        L.amy_batch_query.restype = C.c_int
+        L.amy_batch_solve.argtypes = [pp, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
+                                      C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), ip]
+        L.amy_batch_solve.restype = C.c_int
+        L.amy_tune_solve.argtypes = [pp, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p,
+                                     C.POINTER(TuneResult)]
+        L.amy_tune_solve.restype = C.c_int
+        L.amy_tune_batch.argtypes = [pp, C.c_int32, C.c_void_p, C.c_void_p, C.c_uint64,
+                                     C.POINTER(C.c_void_p), C.POINTER(TuneResult)]
+        L.amy_tune_batch.restype = C.c_int
+        for fn in ("amy_tune_save", "amy_tune_load"):
+            getattr(L, fn).argtypes = [C.c_char_p]
+            getattr(L, fn).restype = C.c_int
+        L.amy_tune_clear.restype = C.c_int
+        L.amy_tune_entries.restype = C.c_int32
         L.amy_last_error.restype = C.c_char_p
         L.amy_version.restype = C.c_char_p
         _lib = L
@@ -200,3 +225,90 @@ def solve(p, policy: bool = True, info: bool = True, budget: int = 0, **kw) -> R
 
 def version() -> str:
     return lib().amy_version().decode()
+
+
+# ------------------------------------------------------------------ batch
+
+def _struct_array(problems, **kw):
+    arr = (ProblemC * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = to_struct(p, **kw)
+    return arr
+
+
+def batch_query(problems, **kw) -> int:
+    arr = _struct_array(problems, **kw)
+    n = C.c_uint64()
+    check(lib().amy_batch_query(arr, len(problems), C.byref(n)))
+    return int(n.value)
+
+
+class BatchSolver:
+    """Device workspace and outputs for repeated batched solves of one set of systems."""
+
+    def __init__(self, problems, device=None, **kw):
+        import torch
+        self.torch = torch
+        self.problems = list(problems)
+        self.arr = _struct_array(self.problems, **kw)
+        self.device = torch.device(device or "cuda")
+        self.ws_bytes = batch_query(self.problems, **kw)
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr = self._ws.data_ptr() + ((-self._ws.data_ptr()) % 256)
+        self.V = [torch.empty(p.n_x, dtype=torch.float64, device=self.device) for p in self.problems]
+        self.vptr = (C.c_void_p * len(self.problems))(*[v.data_ptr() for v in self.V])
+
+    def solve(self, policy: bool = False, info: bool = True, stream=None):
+        torch = self.torch
+        n = len(self.problems)
+        pols = None
+        pptr = None
+        if policy:
+            pols = [torch.empty((p.horizon, p.n_x), dtype=torch.int16, device=self.device)
+                    if p.horizon > 0 else None for p in self.problems]
+            pptr = (C.c_void_p * n)(*[(t.data_ptr() if t is not None else None) for t in pols])
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
+        infos = (Info * n)() if info else None
+        check(lib().amy_batch_solve(self.arr, n, C.c_void_p(st.cuda_stream), C.c_void_p(self.ws_ptr),
+                                    self.ws_bytes, self.vptr, pptr, infos))
+        return [Result(self.V[i], pols[i] if pols else None, infos[i].as_dict() if info else None)
+                for i in range(n)]
+
+    def tune(self, stream=None) -> dict:
+        st = stream if stream is not None else self.torch.cuda.current_stream(self.device)
+        r = TuneResult()
+        check(lib().amy_tune_batch(self.arr, len(self.problems), C.c_void_p(st.cuda_stream),
+                                   C.c_void_p(self.ws_ptr), self.ws_bytes, self.vptr, C.byref(r)))
+        return r.as_dict()
+
+
+def batch_solve(problems, policy: bool = False, info: bool = True, **kw):
+    return BatchSolver(problems, **kw).solve(policy=policy, info=info)
+
+
+# -------------------------------------------------------------- autotuner
+
+def tune_solve(p, **kw) -> dict:
+    s = Solver(p, **kw)
+    V = s.torch.empty(p.n_x, dtype=s.torch.float64, device=s.device)
+    st = s.torch.cuda.current_stream(s.device)
+    r = TuneResult()
+    check(lib().amy_tune_solve(C.byref(s.s), C.c_void_p(st.cuda_stream), C.c_void_p(s.ws_ptr), s.ws_bytes,
+                               C.c_void_p(V.data_ptr()), C.byref(r)))
+    return r.as_dict()
+
+
+def tune_save(path: str):
+    check(lib().amy_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str):
+    check(lib().amy_tune_load(os.fsencode(path)))
+
+
+def tune_clear():
+    check(lib().amy_tune_clear())
+
+
+def tune_entries() -> int:
+    return int(lib().amy_tune_entries())

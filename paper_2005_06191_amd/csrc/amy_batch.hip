@@ -1,0 +1,315 @@
+// amy_batch.hip -- many systems of uneven sizes in one launch.
+//
+// k_batch_persistent: one cooperative launch runs every Bellman step of
+// every system.  Systems are sorted by horizon (longest first), so the
+// systems still active at global step s form a prefix; the work items of a
+// phase are their 64-state tiles.  Workgroups (one wave each) take items
+// from atomic work queues -- one queue per XCD over a contiguous item range,
+// stealing from the other XCDs' queues when their own is empty -- and a
+// grid-wide barrier separates the phases (init, then step 0 .. maxT-1).
+// Every barrier wait is bounded: a wave that waits too long records an
+// error and carries on, so the grid always drains.
+//
+// k_batch_step: one Bellman step for every system of a table (the serving
+// loop's captured step); items are dealt to workgroups by a fixed stride.
+//
+// Each tile runs exactly the single-system kernels' per-state code
+// (sweep_tile / stored_tile), so a system's result does not depend on what
+// it is batched with.
+#include <hip/hip_runtime.h>
+
+#include "amy_generic.hpp"
+
+#define BATCH_BLOCK 64
+
+// The (dynamics, dimension) pairs a batched launch can hold.
+#define AMY_BATCH_FAMILIES(X)                                                                    \
+  X(AMY_DYN_AFFINE_, 1) X(AMY_DYN_AFFINE_, 2) X(AMY_DYN_AFFINE_, 3) X(AMY_DYN_AFFINE_, 4)         \
+  X(AMY_DYN_UNICYCLE_, 3) X(AMY_DYN_ROOM_, 2) X(AMY_DYN_ROOM_, 3) X(AMY_DYN_ROOM_, 4)             \
+  X(AMY_DYN_ROOM_, 5) X(AMY_DYN_VEHICLE7_, 7)
+
+// Out-of-line entry to the single-system per-state code, so that each
+// (family, dimension, precision) instance gets its own register
+// allocation inside the batched kernels.
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+__device__ __noinline__ void tile_call(const DevProblem& P, uint32_t s, const VI* Vin, VO* Vout,
+                                       const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                       unsigned char* smem) {
+  sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
+}
+
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G>
+__device__ __noinline__ void group_call(const DevProblem& P, uint32_t tile, const VI* Vin, VO* Vout,
+                                        const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                        unsigned char* smem) {
+  sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, tile, Vin, Vout, label, pol, tailmax, smem);
+}
+
+template <int N, class MT, class AT, class VI, class VO, bool COMP>
+__device__ __noinline__ void stored_call(const DevProblem& P, uint32_t s, const MT* T, const int32_t* org,
+                                         const VI* Vin, VO* Vout, const uint8_t* label, int16_t* pol) {
+  stored_tile<N, MT, AT, VI, VO, COMP>(P, s, T, org, Vin, Vout, label, pol);
+}
+
+// Calls the per-state code of variant LANES (G == 1: s is the state) or of
+// a group variant (G lanes per state: s is the tile of 64/G states).
+template <int KIND, int N, int G, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+__device__ __forceinline__ void call_variant(const DevProblem& P, uint32_t s, const VI* Vin, VO* Vout,
+                                             const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                             unsigned char* smem) {
+  if constexpr (G == 1)
+    tile_call<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
+  else
+    group_call<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, s, Vin, Vout, label, pol, tailmax, smem);
+}
+
+template <int KIND, int N, int G, bool F64>
+__device__ __forceinline__ void run_otf_g(const BatchSys& B, uint32_t s, int t, unsigned char* smem) {
+  const DevProblem& P = B.P;
+  const int k = B.horizon - t;
+  const bool first = (t == 0) && B.want_tail, last = (k == 1);
+  int16_t* pol = B.pol ? B.pol + (int64_t)(k - 1) * P.n_x : nullptr;
+  if constexpr (F64) {
+    const double* Vin = (const double*)((t & 1) ? B.V1 : B.V0);
+    double* Vo = last ? B.Vout : (double*)((t & 1) ? B.V0 : B.V1);
+    if (first) call_variant<KIND, N, G, double, double, double, double, false, true>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
+    else call_variant<KIND, N, G, double, double, double, double, false, false>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
+  } else {
+    const float* Vin = (const float*)((t & 1) ? B.V1 : B.V0);
+    if (last) {
+      double* Vo = B.Vout;
+      if (first) call_variant<KIND, N, G, float, double, float, double, false, true>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
+      else call_variant<KIND, N, G, float, double, float, double, false, false>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
+    } else {
+      float* Vo = (float*)((t & 1) ? B.V0 : B.V1);
+      if (first) call_variant<KIND, N, G, float, float, float, float, true, true>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
+      else call_variant<KIND, N, G, float, float, float, float, true, false>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
+    }
+  }
+}
+
+template <int KIND, int N, bool F64>
+__device__ __forceinline__ void run_otf(const BatchSys& B, uint32_t tile, int t, unsigned char* smem) {
+  switch (B.P.grp_g) {
+    case 16: run_otf_g<KIND, N, 16, F64>(B, tile, t, smem); return;
+    case 64: run_otf_g<KIND, N, 64, F64>(B, tile, t, smem); return;
+    default: run_otf_g<KIND, N, 1, F64>(B, tile * BATCH_BLOCK + (threadIdx.x & 63), t, smem); return;
+  }
+}
+
+template <int N, bool F64>
+__device__ __forceinline__ void run_stored(const BatchSys& B, uint32_t s, int t) {
+  const DevProblem& P = B.P;
+  const int k = B.horizon - t;
+  const bool last = (k == 1);
+  int16_t* pol = B.pol ? B.pol + (int64_t)(k - 1) * P.n_x : nullptr;
+  if constexpr (F64) {
+    stored_call<N, double, double, double, double, false>(P, s, (const double*)B.T, B.org,
+                                                          (const double*)((t & 1) ? B.V1 : B.V0),
+                                                          last ? B.Vout : (double*)((t & 1) ? B.V0 : B.V1),
+                                                          B.label, pol);
+  } else if (last) {
+    stored_call<N, float, double, float, double, false>(P, s, (const float*)B.T, B.org,
+                                                        (const float*)((t & 1) ? B.V1 : B.V0), B.Vout, B.label, pol);
+  } else {
+    stored_call<N, float, float, float, float, true>(P, s, (const float*)B.T, B.org,
+                                                     (const float*)((t & 1) ? B.V1 : B.V0),
+                                                     (float*)((t & 1) ? B.V0 : B.V1), B.label, pol);
+  }
+}
+
+// One tile of system B at its local step t (0 = the step k = T_d).
+template <bool F64>
+__device__ __forceinline__ void run_tile(const BatchSys& B, uint32_t tile, int t, unsigned char* smem) {
+  const uint32_t s = tile * BATCH_BLOCK + (threadIdx.x & 63);
+  if (B.mode == 1) {  // AMY_MODE_STORED: rows were built at admission
+    switch (B.P.n) {
+      case 1: run_stored<1, F64>(B, s, t); return;
+      case 2: run_stored<2, F64>(B, s, t); return;
+      case 3: run_stored<3, F64>(B, s, t); return;
+      case 4: run_stored<4, F64>(B, s, t); return;
+      case 5: run_stored<5, F64>(B, s, t); return;
+      case 7: run_stored<7, F64>(B, s, t); return;
+    }
+    return;
+  }
+  switch (B.P.kind * 16 + B.P.n) {
+#define X(K, N_) \
+  case K * 16 + N_: run_otf<K, N_, F64>(B, tile, t, smem); return;
+    AMY_BATCH_FAMILIES(X)
+#undef X
+  }
+}
+
+bool amy_batch_supports(int kind, int n, int mode) {
+  if (mode == 1) return n == 1 || n == 2 || n == 3 || n == 4 || n == 5 || n == 7;
+#define X(K, N_) \
+  if (kind == K && n == N_) return true;
+  AMY_BATCH_FAMILIES(X)
+#undef X
+  return false;
+}
+
+template <bool F64>
+__device__ __forceinline__ void init_tile(const BatchSys& B, uint32_t tile) {
+  const uint32_t s = tile * BATCH_BLOCK + (threadIdx.x & 63);
+  if (tile == 0 && threadIdx.x == 0 && B.tailmax) *B.tailmax = 0ull;
+  if (s >= (uint32_t)B.P.n_x) return;
+  double v;
+  B.label[s] = init_state(B.P, s, v);
+  if constexpr (F64) ((double*)B.V0)[s] = v;
+  else ((float*)B.V0)[s] = (float)v;
+  if (B.horizon == 0) B.Vout[s] = v;
+}
+
+// Item i of a phase -> (system, tile) through the tile prefix sums.
+__device__ __forceinline__ int find_sys(const int32_t* __restrict__ tprefix, int nsys, uint32_t item) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((uint32_t)tprefix[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Grid-wide barrier over nblocks co-resident workgroups.  Agent-scope
+// fences publish each workgroup's V writes to every XCD before the
+// generation advances.  Bounded wait: on timeout the error flag is set.
+__device__ __forceinline__ void grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned& gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned a = atomicAdd(&ctl->bar_count, 1u);
+    if (a == nblocks - 1) {
+      atomicExch(&ctl->bar_count, 0u);
+      __threadfence();
+      atomicAdd(&ctl->bar_gen, 1u);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 25)) {
+          atomicOr(&ctl->err, 1u);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  ++gen;
+  __syncthreads();
+}
+
+// Next chunk of items of a phase: this XCD's queue first, then the others'.
+// Item range of XCD q: [q*n/8, (q+1)*n/8).  Returns false when all are done.
+__device__ __forceinline__ bool grab(BatchCtl* ctl, int phase, uint32_t nitems, int chunk, bool xcd_order,
+                                     int& q, uint32_t& first, uint32_t& last) {
+  while (q < 8) {
+    unsigned v = 0;
+    const int qq = xcd_order ? ((int)(blockIdx.x & 7u) + q) & 7 : 0;
+    const uint32_t lo = xcd_order ? (uint32_t)(((uint64_t)nitems * qq) / 8) : 0u;
+    const uint32_t hi = xcd_order ? (uint32_t)(((uint64_t)nitems * (qq + 1)) / 8) : nitems;
+    if ((threadIdx.x & 63) == 0) v = atomicAdd(&ctl->ctr[phase * 8 + qq], (unsigned)chunk);
+    v = __shfl(v, 0);
+    if (lo + v < hi) {
+      first = lo + v;
+      last = min(hi, first + (uint32_t)chunk);
+      return true;
+    }
+    if (!xcd_order) return false;
+    ++q;
+  }
+  return false;
+}
+
+template <bool F64>
+__global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) k_batch_persistent(const BatchSys* __restrict__ sys, int nsys,
+                                                                  const int32_t* __restrict__ tprefix,
+                                                                  const int32_t* __restrict__ active,
+                                                                  int max_steps, BatchCtl* ctl, int chunk,
+                                                                  int xcd_order) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned gen = 0;
+  for (int phase = 0; phase <= max_steps; ++phase) {
+    const int nact = (phase == 0) ? nsys : active[phase - 1];
+    const uint32_t nitems = (uint32_t)tprefix[nact];
+    int q = 0;
+    uint32_t first, last;
+    while (grab(ctl, phase, nitems, chunk, xcd_order != 0, q, first, last)) {
+      for (uint32_t it = first; it < last; ++it) {
+        const int j = find_sys(tprefix, nact, it);
+        const BatchSys& B = sys[j];
+        const uint32_t tile = it - (uint32_t)tprefix[j];
+        if (phase == 0) init_tile<F64>(B, tile);
+        else run_tile<F64>(B, tile, phase - 1, smem);
+      }
+    }
+    if (phase < max_steps) grid_barrier(ctl, gridDim.x, gen);
+  }
+}
+
+// One step of every listed system; BatchSys::step_base holds the system's
+// local step t for this launch (written by the host before each replay).
+template <bool F64>
+__global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) k_batch_step(const BatchSys* __restrict__ sys, int nsys,
+                                                            const int32_t* __restrict__ tprefix) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t nitems = (uint32_t)tprefix[nsys];
+  for (uint32_t it = xcd_block(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
+    const int j = find_sys(tprefix, nsys, it);
+    const BatchSys& B = sys[j];
+    if (B.step_base < 0 || B.step_base >= B.horizon) continue;
+    run_tile<F64>(B, it - (uint32_t)tprefix[j], B.step_base, smem);
+  }
+}
+
+template <bool F64>
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_init(const BatchSys* __restrict__ sys, int nsys,
+                                                            const int32_t* __restrict__ tprefix) {
+  const uint32_t nitems = (uint32_t)tprefix[nsys];
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int j = find_sys(tprefix, nsys, it);
+    init_tile<F64>(sys[j], it - (uint32_t)tprefix[j]);
+  }
+}
+
+__global__ void k_fill_u32(unsigned* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// ------------------------------------------------------------- launchers
+
+const void* amy_batch_persistent_kernel(bool f64) {
+  return f64 ? (const void*)&k_batch_persistent<true> : (const void*)&k_batch_persistent<false>;
+}
+
+hipError_t amy_launch_batch_persistent(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
+                                       const int32_t* tprefix, const int32_t* active, int max_steps,
+                                       BatchCtl* ctl, int chunk, int xcd_order, hipStream_t st) {
+  void* args[] = {(void*)&sys, (void*)&nsys, (void*)&tprefix, (void*)&active, (void*)&max_steps,
+                  (void*)&ctl, (void*)&chunk, (void*)&xcd_order};
+  return hipLaunchCooperativeKernel(amy_batch_persistent_kernel(f64), dim3(grid), dim3(BATCH_BLOCK), args,
+                                    (unsigned)lds, st);
+}
+
+hipError_t amy_launch_batch_step(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
+                                 const int32_t* tprefix, hipStream_t st) {
+  if (f64) hipLaunchKernelGGL((k_batch_step<true>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, nsys, tprefix);
+  else hipLaunchKernelGGL((k_batch_step<false>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, nsys, tprefix);
+  return hipGetLastError();
+}
+
+hipError_t amy_launch_batch_init(bool f64, const BatchSys* sys, int nsys, const int32_t* tprefix, unsigned grid,
+                                 hipStream_t st) {
+  if (f64) hipLaunchKernelGGL((k_batch_init<true>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tprefix);
+  else hipLaunchKernelGGL((k_batch_init<false>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tprefix);
+  return hipGetLastError();
+}
+
+hipError_t amy_launch_fill_u32(unsigned* p, size_t n, hipStream_t st) {
+  const unsigned g = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+  hipLaunchKernelGGL(k_fill_u32, dim3(g > 0 ? g : 1), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}

@@ -1,0 +1,18 @@
+// amy_batch.hpp -- host-side entry points of the batched kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "amy_plan.hpp"
+
+bool amy_batch_supports(int kind, int n, int mode);
+const void* amy_batch_persistent_kernel(bool f64);
+hipError_t amy_launch_batch_persistent(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
+                                       const int32_t* tprefix, const int32_t* active, int max_steps,
+                                       BatchCtl* ctl, int chunk, int xcd_order, hipStream_t st);
+hipError_t amy_launch_batch_step(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
+                                 const int32_t* tprefix, hipStream_t st);
+hipError_t amy_launch_batch_init(bool f64, const BatchSys* sys, int nsys, const int32_t* tprefix, unsigned grid,
+                                 hipStream_t st);
+hipError_t amy_launch_fill_u32(unsigned* p, size_t n, hipStream_t st);

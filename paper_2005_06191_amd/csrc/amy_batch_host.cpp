@@ -1,0 +1,205 @@
+// amy_batch_host.cpp -- C ABI of the batched solve: many systems, one
+// cooperative persistent launch.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/amytiss.h"
+#include "amy_batch.hpp"
+#include "amy_host.hpp"
+#include "amy_kernels.hpp"
+#include "amy_tune.hpp"
+
+static inline uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp) {
+  if (!probs || count < 1 || count > AMY_BATCH_MAX)
+    return amy_fail(AMY_E_INVALID, "batch of %d systems (1..%d)", count, AMY_BATCH_MAX);
+  bp.plans.assign(count, Plan());
+  bp.lds = 0;
+  bp.maxT = 0;
+  for (int i = 0; i < count; ++i) {
+    amy_status st = amy_validate(&probs[i]);
+    if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
+    amy_problem q = probs[i];
+    if (q.mode == AMY_MODE_STORED)
+      return amy_fail(AMY_E_UNSUPPORTED, "system %d: the batched launch recomputes rows (OTF mode only)", i);
+    q.mode = AMY_MODE_OTF;
+    if (q.variant == AMY_VARIANT_FIXED) q.variant = AMY_VARIANT_LANES;
+    st = amy_resolve(&q, 0, &bp.plans[i]);
+    if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
+    // the compiled-shape sweep is not part of the batched kernel; LANES
+    // computes the same bits
+    if (bp.plans[i].dev.variant == AMY_VARIANT_FIXED) bp.plans[i].dev.variant = AMY_VARIANT_LANES;
+    const DevProblem& D = bp.plans[i].dev;
+    if (!amy_batch_supports(D.kind, D.n, AMY_MODE_OTF))
+      return amy_fail(AMY_E_UNSUPPORTED, "system %d: dynamics kind %d with n=%d is not compiled into the batched kernel",
+                      i, D.kind, D.n);
+    if (i == 0) bp.f64 = bp.plans[i].f64;
+    else if (bp.plans[i].f64 != bp.f64)
+      return amy_fail(AMY_E_UNSUPPORTED, "system %d: a batch runs in one precision", i);
+    if (probs[i].horizon > AMY_BATCH_MAX_STEPS)
+      return amy_fail(AMY_E_UNSUPPORTED, "system %d: horizon %d > %d", i, probs[i].horizon, AMY_BATCH_MAX_STEPS);
+    bp.maxT = std::max(bp.maxT, (int)probs[i].horizon);
+    bp.lds = std::max(bp.lds, (size_t)(D.grp_g > 1 ? D.lds_bytes_group : D.lds_bytes_tail));
+  }
+  // longest horizon first: the systems still running at global step s are a prefix
+  bp.order.resize(count);
+  for (int i = 0; i < count; ++i) bp.order[i] = i;
+  std::stable_sort(bp.order.begin(), bp.order.end(),
+                   [&](int a, int b) { return probs[a].horizon > probs[b].horizon; });
+  bp.tprefix.assign(count + 1, 0);
+  for (int r = 0; r < count; ++r) {
+    const DevProblem& D = bp.plans[bp.order[r]].dev;
+    const int per_tile = 64 / std::max(1, (int)D.grp_g);  // states per 64-lane tile
+    bp.tprefix[r + 1] = bp.tprefix[r] + (int32_t)((D.n_x + per_tile - 1) / per_tile);
+  }
+  bp.active.assign(std::max(bp.maxT, 1), 0);
+  for (int s = 0; s < bp.maxT; ++s) {
+    int a = 0;
+    while (a < count && probs[bp.order[a]].horizon > s) ++a;
+    bp.active[s] = a;
+  }
+  uint64_t o = 0;
+  bp.off_sys = o;  o = al256(o + (uint64_t)count * sizeof(BatchSys));
+  bp.off_tp = o;   o = al256(o + (uint64_t)(count + 1) * 4);
+  bp.off_act = o;  o = al256(o + (uint64_t)bp.active.size() * 4);
+  bp.off_ctl = o;  o = al256(o + sizeof(BatchCtl));
+  bp.base.assign(count, 0);
+  for (int i = 0; i < count; ++i) {
+    bp.base[i] = o;
+    o = al256(o + bp.plans[i].ws_bytes);
+  }
+  bp.ws_bytes = o;
+  return AMY_OK;
+}
+
+void amy_batch_fill(const amy_problem* probs, const BatchPlan& bp, char* ws, double* const* V_out,
+                    int16_t* const* policy_out, bool want_tail, std::vector<BatchSys>& sys) {
+  const int count = (int)bp.plans.size();
+  sys.assign(count, BatchSys());
+  for (int r = 0; r < count; ++r) {
+    const int i = bp.order[r];
+    const Plan& pl = bp.plans[i];
+    BatchSys& B = sys[r];
+    memset(&B, 0, sizeof B);
+    B.P = pl.dev;
+    char* b = ws + bp.base[i];
+    B.label = (uint8_t*)(b + pl.off_label);
+    B.V0 = b + pl.off_v0;
+    B.V1 = b + pl.off_v1;
+    B.tailmax = (unsigned long long*)(b + pl.off_tail);
+    B.Vout = V_out[i];
+    B.pol = policy_out ? policy_out[i] : nullptr;
+    B.horizon = probs[i].horizon;
+    B.tiles = (int32_t)((pl.dev.n_x + 64 / pl.dev.grp_g - 1) / (64 / pl.dev.grp_g));
+    B.mode = AMY_MODE_OTF;
+    B.want_tail = want_tail ? 1 : 0;
+  }
+}
+
+extern "C" amy_status amy_batch_query(const amy_problem* probs, int32_t count, uint64_t* ws_bytes) {
+  BatchPlan bp;
+  amy_status st = amy_batch_plan(probs, count, bp);
+  if (st != AMY_OK) return st;
+  if (ws_bytes) *ws_bytes = bp.ws_bytes;
+  return AMY_OK;
+}
+
+amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStream_t hs, char* ws,
+                         double* const* V_out, int16_t* const* policy_out, bool want_tail, const BatchTune& tune,
+                         float* ms_out) {
+  const int count = (int)bp.plans.size();
+  std::vector<BatchSys> sys;
+  amy_batch_fill(probs, bp, ws, V_out, policy_out, want_tail, sys);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(ws + bp.off_sys, sys.data(), sizeof(BatchSys) * count, hipMemcpyHostToDevice, hs)) ||
+      (e = hipMemcpyAsync(ws + bp.off_tp, bp.tprefix.data(), 4 * bp.tprefix.size(), hipMemcpyHostToDevice, hs)) ||
+      (e = hipMemcpyAsync(ws + bp.off_act, bp.active.data(), 4 * bp.active.size(), hipMemcpyHostToDevice, hs)))
+    return amy_hip_fail(e, "batch tables upload");
+  if ((e = amy_launch_fill_u32((unsigned*)(ws + bp.off_ctl), sizeof(BatchCtl) / 4, hs)) != hipSuccess)
+    return amy_hip_fail(e, "batch control reset");
+  int dev = 0, ncu = 0, occ = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_persistent_kernel(bp.f64), 64, bp.lds);
+  if (e != hipSuccess || occ < 1) return amy_hip_fail(e, "batch occupancy query");
+  const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
+  const unsigned grid = (unsigned)std::max(1, ncu * bpc);
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (ms_out) {
+    hipEventCreate(&ev[0]);
+    hipEventCreate(&ev[1]);
+    hipEventRecord(ev[0], hs);
+  }
+  e = amy_launch_batch_persistent(bp.f64, grid, bp.lds, (const BatchSys*)(ws + bp.off_sys), count,
+                                  (const int32_t*)(ws + bp.off_tp), (const int32_t*)(ws + bp.off_act), bp.maxT,
+                                  (BatchCtl*)(ws + bp.off_ctl), std::max(1, tune.chunk), tune.xcd_order, hs);
+  if (e != hipSuccess) {
+    if (ms_out) {
+      hipEventDestroy(ev[0]);
+      hipEventDestroy(ev[1]);
+    }
+    return amy_hip_fail(e, "batch cooperative launch");
+  }
+  if (ms_out) {
+    hipEventRecord(ev[1], hs);
+    hipEventSynchronize(ev[1]);
+    hipEventElapsedTime(ms_out, ev[0], ev[1]);
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+  }
+  return AMY_OK;
+}
+
+extern "C" amy_status amy_batch_solve(const amy_problem* probs, int32_t count, void* stream, void* workspace,
+                                      uint64_t ws_bytes, double* const* V_out, int16_t* const* policy_out,
+                                      amy_info* infos) {
+  BatchPlan bp;
+  amy_status st = amy_batch_plan(probs, count, bp);
+  if (st != AMY_OK) return st;
+  if (!workspace || ((uintptr_t)workspace & 255)) return amy_fail(AMY_E_INVALID, "workspace NULL or not 256-byte aligned");
+  if (ws_bytes < bp.ws_bytes)
+    return amy_fail(AMY_E_NOMEM, "batch workspace %llu B < %llu B", (unsigned long long)ws_bytes,
+                    (unsigned long long)bp.ws_bytes);
+  if (!V_out) return amy_fail(AMY_E_INVALID, "V_out is NULL");
+  for (int i = 0; i < count; ++i)
+    if (!V_out[i]) return amy_fail(AMY_E_INVALID, "V_out[%d] is NULL", i);
+  hipStream_t hs = (hipStream_t)stream;
+  BatchTune tune = amy_tune_lookup_batch(probs, count, bp);
+  float ms = 0.f;
+  st = amy_batch_run(probs, bp, hs, (char*)workspace, V_out, policy_out, infos != nullptr, tune,
+                     infos ? &ms : nullptr);
+  if (st != AMY_OK || !infos) return st;
+  BatchCtl ctl;
+  hipError_t e = hipMemcpy(&ctl, (char*)workspace + bp.off_ctl, 16, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return amy_hip_fail(e, "batch control readback");
+  if (ctl.err) return amy_fail(AMY_E_DEVICE, "batch grid barrier timed out (results invalid)");
+  for (int i = 0; i < count; ++i) {
+    amy_info& inf = infos[i];
+    memset(&inf, 0, sizeof inf);
+    const Plan& pl = bp.plans[i];
+    inf.mode_used = AMY_MODE_OTF;
+    inf.kernel = pl.dev.variant;
+    for (int d = 0; d < pl.dev.n; ++d) inf.window[d] = pl.dev.L[d];
+    for (int d = 0; d < pl.dev.n; ++d)
+      if (pl.dev.ccount[d] > 0) inf.table_cache_mask |= 1 << d;
+    inf.lds_bytes = pl.dev.lds_bytes;
+    inf.n_x = pl.dev.n_x;
+    inf.n_u = pl.dev.n_u;
+    inf.rows = pl.rows;
+    inf.W = pl.W;
+    inf.workspace_bytes = bp.ws_bytes;
+    unsigned long long bits = 0;
+    e = hipMemcpy(&bits, (char*)workspace + bp.base[i] + pl.off_tail, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return amy_hip_fail(e, "tail readback");
+    double t;
+    memcpy(&t, &bits, 8);
+    inf.max_row_tail = probs[i].horizon > 0 ? t : 0.0;
+    inf.tail_bound_E = inf.max_row_tail * probs[i].horizon;
+    inf.t_sweeps_ms = inf.t_total_ms = ms;
+  }
+  return AMY_OK;
+}

@@ -46,3 +46,19 @@ hipError_t amy_gen_affine_build(const DevProblem& P, bool f64, const uint8_t* la
   }
   return hipErrorInvalidValue;
 }
+
+hipError_t amy_gen_affine_group(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                               const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                               hipStream_t st) {
+  switch (P.n) {
+    case 1: return Launch<AMY_DYN_AFFINE_, 1>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 2: return Launch<AMY_DYN_AFFINE_, 2>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 3: return Launch<AMY_DYN_AFFINE_, 3>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 4: return Launch<AMY_DYN_AFFINE_, 4>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 5: return Launch<AMY_DYN_AFFINE_, 5>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 6: return Launch<AMY_DYN_AFFINE_, 6>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 7: return Launch<AMY_DYN_AFFINE_, 7>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+    case 8: return Launch<AMY_DYN_AFFINE_, 8>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+  }
+  return hipErrorInvalidValue;
+}

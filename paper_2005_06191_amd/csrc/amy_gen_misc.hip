@@ -51,3 +51,17 @@ hipError_t amy_gen_vehicle7_build(const DevProblem& P, bool f64, const uint8_t* 
   }
   return hipErrorInvalidValue;
 }
+
+hipError_t amy_gen_unicycle_group(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                               const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                               hipStream_t st) {
+  if (P.n == 3) return Launch<AMY_DYN_UNICYCLE_, 3>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t amy_gen_vehicle7_group(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                               const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                               hipStream_t st) {
+  if (P.n == 7) return Launch<AMY_DYN_VEHICLE7_, 7>::group(P, sk, Vin, Vout, label, pol, tailmax, st);
+  return hipErrorInvalidValue;
+}

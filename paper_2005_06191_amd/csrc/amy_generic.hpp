@@ -21,21 +21,18 @@
 #include <hip/hip_runtime.h>
 
 #include "amy_device.hpp"
+#include "amy_group.hpp"
 #include "amy_kernels.hpp"
 
 #define LANE_BLOCK 64
 
 // ------------------------------------------------------------------ init
 
-template <class VT>
-__global__ void __launch_bounds__(256) k_init(DevProblem P, uint8_t* __restrict__ label,
-                                              VT* __restrict__ V0, double* __restrict__ Vout,
-                                              unsigned long long* __restrict__ tailmax) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0 && tailmax) *tailmax = 0ull;
-  if (s >= P.n_x) return;
+// Label of state s (free / fixed 0 / fixed 1, by its cell centre) and its
+// terminal value V_{T_d+1} in the extended representation.
+__device__ __forceinline__ uint8_t init_state(const DevProblem& P, uint32_t s, double& v) {
   double x[AMY_MAXD];
-  uint32_t r = (uint32_t)s;
+  uint32_t r = s;
 #pragma unroll
   for (int i = AMY_MAXD - 1; i >= 0; --i) {
     if (i < P.n) {
@@ -54,22 +51,31 @@ __global__ void __launch_bounds__(256) k_init(DevProblem P, uint8_t* __restrict_
       in_s = in_s && (x[i] >= P.slo[i] && x[i] <= P.shi[i]);
     }
   }
-  uint8_t lb;
-  double v;
   if (P.spec == 0) {
-    lb = in_s ? LBL_FREE : LBL_ZERO;
     v = in_s ? 1.0 : 0.0;
-  } else if (P.spec == 2 && in_a) {
-    lb = LBL_ZERO;
-    v = 0.0;
-  } else if (in_t) {
-    lb = LBL_ONE;
-    v = 1.0;
-  } else {
-    lb = LBL_FREE;
-    v = 0.0;
+    return in_s ? LBL_FREE : LBL_ZERO;
   }
-  label[s] = lb;
+  if (P.spec == 2 && in_a) {
+    v = 0.0;
+    return LBL_ZERO;
+  }
+  if (in_t) {
+    v = 1.0;
+    return LBL_ONE;
+  }
+  v = 0.0;
+  return LBL_FREE;
+}
+
+template <class VT>
+__global__ void __launch_bounds__(256) k_init(DevProblem P, uint8_t* __restrict__ label,
+                                              VT* __restrict__ V0, double* __restrict__ Vout,
+                                              unsigned long long* __restrict__ tailmax) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0 && tailmax) *tailmax = 0ull;
+  if (s >= P.n_x) return;
+  double v;
+  label[s] = init_state(P, (uint32_t)s, v);
   V0[s] = (VT)v;
   if (Vout) Vout[s] = v;
 }
@@ -123,15 +129,14 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_tail(DevProblem P, const uint8_t
 // Vin / Vout hold extended values (1 on T\A, 0 on A and outside S), so the
 // reach / reach-avoid T0 term of Alg. 4 is the window mass on target cells.
 // TAIL (first step only): also the FP64 max row tail into *tailmax.
+// The sweep of one state s (one lane); the whole wave must call it (the tail
+// pass ends in a wave reduction).
 template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
-__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_otf(DevProblem P, const VI* __restrict__ Vin,
-                                                          VO* __restrict__ Vout,
-                                                          const uint8_t* __restrict__ label,
-                                                          int16_t* __restrict__ pol,
-                                                          unsigned long long* __restrict__ tailmax) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const LaneLds<MT> S(P, smem, threadIdx.x);
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
+__device__ __forceinline__ void sweep_tile(const DevProblem& P, uint32_t s, const VI* __restrict__ Vin,
+                                           VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                           int16_t* __restrict__ pol, unsigned long long* __restrict__ tailmax,
+                                           unsigned char* smem) {
+  const LaneLds<MT> S(P, smem, threadIdx.x & 63);
   double tmax = 0.0;
   if (s < (uint32_t)P.n_x) {
     const uint8_t lb = label[s];
@@ -170,6 +175,28 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_sweep_otf(DevProblem P, const VI
     }
   }
   if constexpr (TAIL) wave_max_to(tmax, tailmax);
+}
+
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_otf(DevProblem P, const VI* __restrict__ Vin,
+                                                          VO* __restrict__ Vout,
+                                                          const uint8_t* __restrict__ label,
+                                                          int16_t* __restrict__ pol,
+                                                          unsigned long long* __restrict__ tailmax) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
+  sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
+}
+
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G>
+__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_group(DevProblem P, const VI* __restrict__ Vin,
+                                                            VO* __restrict__ Vout,
+                                                            const uint8_t* __restrict__ label,
+                                                            int16_t* __restrict__ pol,
+                                                            unsigned long long* __restrict__ tailmax) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, xcd_block(blockIdx.x, gridDim.x), Vin, Vout, label, pol,
+                                                      tailmax, smem);
 }
 
 // --------------------------------------------------------------- stored
@@ -252,13 +279,10 @@ __device__ __forceinline__ void stored_sum(const DevProblem& P, const MT* __rest
 }
 
 template <int N, class MT, class AT, class VI, class VO, bool COMP>
-__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_stored(DevProblem P, const MT* __restrict__ T,
-                                                             const int32_t* __restrict__ org,
-                                                             const VI* __restrict__ Vin,
-                                                             VO* __restrict__ Vout,
-                                                             const uint8_t* __restrict__ label,
-                                                             int16_t* __restrict__ pol) {
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
+__device__ __forceinline__ void stored_tile(const DevProblem& P, uint32_t s, const MT* __restrict__ T,
+                                            const int32_t* __restrict__ org, const VI* __restrict__ Vin,
+                                            VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                            int16_t* __restrict__ pol) {
   if (s >= (uint32_t)P.n_x) return;
   const uint8_t lb = label[s];
   if (lb != LBL_FREE) {
@@ -282,6 +306,17 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_sweep_stored(DevProblem P, const
   }
   Vout[s] = VO(best);
   if (pol) pol[s] = (int16_t)arg;
+}
+
+template <int N, class MT, class AT, class VI, class VO, bool COMP>
+__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_stored(DevProblem P, const MT* __restrict__ T,
+                                                             const int32_t* __restrict__ org,
+                                                             const VI* __restrict__ Vin,
+                                                             VO* __restrict__ Vout,
+                                                             const uint8_t* __restrict__ label,
+                                                             int16_t* __restrict__ pol) {
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
+  stored_tile<N, MT, AT, VI, VO, COMP>(P, s, T, org, Vin, Vout, label, pol);
 }
 
 template <class VT>
@@ -340,6 +375,32 @@ struct Launch {
       case SWEEP_F32: sweep_t<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, st); break;
       case SWEEP_F32_LAST: sweep_t<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, st); break;
     }
+    return hipGetLastError();
+  }
+  template <class MT, class AT, class VI, class VO, bool COMP, int G>
+  static void group_t(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                      unsigned long long* tailmax, hipStream_t st) {
+    const dim3 g((unsigned)((P.n_x + (64 / G) - 1) / (64 / G))), b(LANE_BLOCK);
+    if (tailmax)
+      hipLaunchKernelGGL((k_sweep_group<KIND, N, MT, AT, VI, VO, COMP, true, G>), g, b, P.lds_bytes_group, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+    else
+      hipLaunchKernelGGL((k_sweep_group<KIND, N, MT, AT, VI, VO, COMP, false, G>), g, b, P.lds_bytes_group, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+  }
+  template <int G>
+  static void group_g(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout, const uint8_t* label,
+                      int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
+    switch (sk) {
+      case SWEEP_F64: group_t<double, double, double, double, false, G>(P, Vin, Vout, label, pol, tailmax, st); break;
+      case SWEEP_F32: group_t<float, float, float, float, true, G>(P, Vin, Vout, label, pol, tailmax, st); break;
+      case SWEEP_F32_LAST: group_t<float, double, float, double, false, G>(P, Vin, Vout, label, pol, tailmax, st); break;
+    }
+  }
+  static hipError_t group(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout, const uint8_t* label,
+                          int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
+    if (P.grp_g == 64) group_g<64>(P, sk, Vin, Vout, label, pol, tailmax, st);
+    else group_g<16>(P, sk, Vin, Vout, label, pol, tailmax, st);
     return hipGetLastError();
   }
   template <class MT>

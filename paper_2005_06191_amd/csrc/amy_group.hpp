@@ -1,0 +1,154 @@
+// amy_group.hpp -- Bellman sweep with G lanes per state (G = 16 or 64), for
+// windows whose per-lane 1-D tables would not fit in LDS (thousands of
+// cells per row): a wave holds 64/G states; the G lanes of a state build its
+// 1-D tables together (slots split across lanes, kept in the group's LDS
+// region), split the window -- each lane takes lane-space indices (the
+// innermost dimensions from grp_nout on) and contracts the outer
+// dimensions for them -- and combine their partial sums with a butterfly.
+// With G = 64 this is one wavefront per (state, input) row.
+// Loop trip counts and barriers are uniform across the wave (all states of
+// a wave belong to one system); inactive states only skip arithmetic.
+#pragma once
+#include "amy_device.hpp"
+
+// Mass of window slot k of dimension i (both edges evaluated here; the same
+// edge values, clamps and differencing as dim_table).
+template <class MT>
+__device__ __forceinline__ MT slot_mass(const DevProblem& P, int i, const Win& w, int k) {
+  const double z0 = edge_z(P, i, w, min(max(w.o + k, w.jlo), w.b));
+  const double z1 = edge_z(P, i, w, min(max(w.o + k + 1, w.jlo), w.b));
+  return mass_of(z0, ec_of(z0, MT()), z1, ec_of(z1, MT()));
+}
+
+// Outer dimensions (D < nout) contracted, inner digits fixed at kin[].
+template <int D, int N, class MT, class AT, class VT>
+__device__ __forceinline__ AT gsum(const DevProblem& P, int nout, const MT* __restrict__ t, const int* kin,
+                                   const VT* __restrict__ V, int64_t off) {
+  if constexpr (D == N) {
+    return AT(V[off]);
+  } else {
+    if (D < nout) {
+      const MT* td = t + P.goff[D];
+      AT acc = AT(0);
+      for (int k = 0; k < P.L[D]; ++k)
+        acc = fma_(AT(td[k]), gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, off + (int64_t)k * P.stride[D]), acc);
+      return acc;
+    }
+    return gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, off + (int64_t)kin[D] * P.stride[D]);
+  }
+}
+
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G>
+__device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, const VI* __restrict__ Vin,
+                                            VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                            int16_t* __restrict__ pol, unsigned long long* __restrict__ tailmax,
+                                            unsigned char* smem) {
+  constexpr int NG = 64 / G;
+  const int lane = threadIdx.x & 63, g = lane / G, gl = lane % G;
+  const uint32_t s = tile * NG + g;
+  MT* tab = reinterpret_cast<MT*>(smem) + g * P.gsl;
+  const bool inside = s < (uint32_t)P.n_x;
+  const uint8_t lb = inside ? label[s] : (uint8_t)LBL_ZERO;
+  const bool active = inside && lb == LBL_FREE;
+  if (inside && !active && gl == 0) {
+    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
+    if (pol) pol[s] = -1;
+  }
+  double x[N];
+  state_centre<N>(P, inside ? s : 0u, x);
+  typename Dyn<KIND, N>::State st;
+  Dyn<KIND, N>::prep(P, x, st);
+  double prev[N];
+  int o[N];
+  double wmem[TAIL ? N : 1], gmem[TAIL ? N : 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    prev[i] = __builtin_nan("");
+    o[i] = 0;
+  }
+  // lane space: the dimensions from nout on, flattened (last fastest)
+  const int nout = P.grp_nout;
+  int ls = 1;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i >= nout) ls *= P.L[i];
+  InputWalk iw;
+  iw.reset();
+  AT best = AT(-1);
+  int arg = 0;
+  double tmax = 0.0;
+  for (int u = 0; u < P.n_u; ++u) {
+    double uv[AMY_MAXI], mu[N];
+    iw.values(P, uv);
+    Dyn<KIND, N>::apply(P, st, x, uv, mu);
+    double win = 1.0, grid = 1.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (mu[i] != prev[i]) {
+        const Win w = window_1d(P, i, mu[i]);
+        o[i] = w.o;
+        prev[i] = mu[i];
+        if (active)
+          for (int k = gl; k < P.L[i]; k += G) tab[P.goff[i] + k] = slot_mass<MT>(P, i, w, k);
+        if constexpr (TAIL) win_grid_mass(P, i, w, wmem[i], gmem[i]);
+      }
+      if constexpr (TAIL) {
+        win *= wmem[i];
+        grid *= gmem[i];
+      }
+    }
+    __syncthreads();  // tables visible to the whole group (one wave per block)
+    int64_t base = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) base += (int64_t)o[i] * P.stride[i];
+    AT acc = AT(0), cmp = AT(0);
+    if (active) {
+      for (int j = gl; j < ls; j += G) {
+        int kin[N];
+        AT mi = AT(1);
+        int r = j;
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+          if (i >= nout) {
+            const int k = r % P.L[i];
+            r /= P.L[i];
+            kin[i] = k;
+          } else {
+            kin[i] = 0;
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+          if (i >= nout) mi = mi * AT(tab[P.goff[i] + kin[i]]);
+        const AT sj = gsum<0, N, MT, AT, VI>(P, nout, tab, kin, Vin, base);
+        if constexpr (COMP) {
+          const AT y = mi * sj - cmp;
+          const AT s2 = acc + y;
+          cmp = (s2 - acc) - y;
+          acc = s2;
+        } else {
+          acc = fma_(mi, sj, acc);
+        }
+      }
+    }
+    // sum of the group's partials (butterfly inside each group of G lanes)
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (acc > best) {
+      best = acc;
+      arg = u;
+    }
+    if constexpr (TAIL)
+      if (active) tmax = fmax(tmax, grid - win);
+    __syncthreads();  // the group's tables may be rebuilt for the next input
+    iw.next(P);
+  }
+  if (active && gl == 0) {
+    Vout[s] = VO(best);
+    if (pol) pol[s] = (int16_t)arg;
+  }
+  if constexpr (TAIL) {
+    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+    if (lane == 0 && tmax > 0.0) atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+  }
+}

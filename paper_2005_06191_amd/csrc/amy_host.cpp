@@ -11,6 +11,7 @@
 #include "../../include/amytiss.h"
 #include "amy_host.hpp"
 #include "amy_kernels.hpp"
+#include "amy_tune.hpp"
 
 static thread_local std::string g_err;
 
@@ -92,7 +93,7 @@ amy_status amy_validate(const amy_problem* p) {
   if (p->spec < AMY_SAFETY || p->spec > AMY_REACH_AVOID) return amy_fail(AMY_E_INVALID, "bad spec");
   if (p->mode < AMY_MODE_AUTO || p->mode > AMY_MODE_OTF) return amy_fail(AMY_E_INVALID, "bad mode");
   if (p->precision != AMY_FP64 && p->precision != AMY_FP32) return amy_fail(AMY_E_INVALID, "bad precision");
-  if (p->variant < AMY_VARIANT_AUTO || p->variant > AMY_VARIANT_FIXED) return amy_fail(AMY_E_INVALID, "bad variant");
+  if (p->variant < AMY_VARIANT_AUTO || p->variant > AMY_VARIANT_GROUP64) return amy_fail(AMY_E_INVALID, "bad variant");
   const int ep = expected_params(p);
   if (ep < 0) return amy_fail(AMY_E_INVALID, "bad dynamics kind %d", p->dyn.kind);
   if (p->dyn.kind == AMY_DYN_UNICYCLE && (n != 3 || m != 2))
@@ -326,6 +327,25 @@ void amy_layout(Plan* pl, int mode) {
 // erfc's per row, the stored sweep 4W (8W) bytes of HBM traffic; at the
 // chip's ~20 flop/byte balance OTF wins for every built-in family, so AUTO
 // takes OTF.  STORED is used only when asked for explicitly.
+// Group-variant layout for G lanes per state: the state's 1-D tables back to
+// back (gsl entries), 64/G states per block; the lane space is the smallest
+// run of innermost dimensions with at least G cells.
+static void plan_group(Plan* pl, int G) {
+  DevProblem& D = pl->dev;
+  int off = 0;
+  for (int i = 0; i < D.n; ++i) {
+    D.goff[i] = off;
+    off += D.L[i];
+  }
+  D.gsl = (off + 1) & ~1;
+  int64_t cells = 1;
+  int nout = D.n;
+  while (nout > 0 && cells < G) cells *= D.L[--nout];
+  D.grp_g = G;
+  D.grp_nout = nout;
+  D.lds_bytes_group = (64 / G) * D.gsl * (pl->f64 ? 8 : 4);
+}
+
 amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   amy_make_plan(p, pl);
   int mode = p->mode == AMY_MODE_AUTO ? AMY_MODE_OTF : p->mode;
@@ -335,13 +355,50 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   if (budget && pl->ws_bytes > budget)
     return amy_fail(AMY_E_NOMEM, "workspace %llu B exceeds budget %llu B",
                     (unsigned long long)pl->ws_bytes, (unsigned long long)budget);
-  amy_status st = plan_tables(p, pl);
-  if (st != AMY_OK) return st;
-  // sweep variant: the compiled-shape kernel where one exists, unless forced
-  const bool fixed_ok = amy_fixed_available(pl->dev);
-  if (p->variant == AMY_VARIANT_FIXED && !fixed_ok)
-    return amy_fail(AMY_E_UNSUPPORTED, "no compiled kernel for this window shape");
-  pl->dev.variant = (p->variant == AMY_VARIANT_LANES || !fixed_ok) ? AMY_VARIANT_LANES : AMY_VARIANT_FIXED;
+  // variants that fit: one lane per state needs every lane's 1-D tables in
+  // LDS; the group variants need one set per state of the block
+  const bool lanes_ok = (plan_tables(p, pl) == AMY_OK);
+  const bool fixed_ok = lanes_ok && amy_fixed_available(pl->dev);
+  int64_t sum_l = 0;
+  for (int i = 0; i < pl->dev.n; ++i) sum_l += pl->dev.L[i];
+  const int64_t msz = pl->f64 ? 8 : 4;
+  const bool g16_ok = 4 * ((sum_l + 1) & ~1) * msz <= LDS_BUDGET;
+  const bool g64_ok = ((sum_l + 1) & ~1) * msz <= LDS_BUDGET;
+  auto feasible = [&](int v) {
+    switch (v) {
+      case AMY_VARIANT_LANES: return lanes_ok;
+      case AMY_VARIANT_FIXED: return fixed_ok;
+      case AMY_VARIANT_GROUP16: return g16_ok && mode == AMY_MODE_OTF;
+      case AMY_VARIANT_GROUP64: return g64_ok && mode == AMY_MODE_OTF;
+    }
+    return false;
+  };
+  if (mode == AMY_MODE_STORED && !lanes_ok)
+    return amy_fail(AMY_E_UNSUPPORTED, "stored mode: window tables need more LDS than one lane per state allows");
+  int v = p->variant;
+  if (v != AMY_VARIANT_AUTO && !feasible(v))
+    return amy_fail(AMY_E_UNSUPPORTED, "sweep variant %d does not fit this problem", v);
+  if (v == AMY_VARIANT_AUTO) {
+    const int t = amy_tune_lookup_variant(*pl, p);  // tuned choice, if any
+    if (t != AMY_VARIANT_AUTO && feasible(t)) v = t;
+  }
+  if (v == AMY_VARIANT_AUTO) {
+    // one lane per state while its tables leave room for >= 6 waves per CU
+    // and the window is small; otherwise lanes share a state's window
+    const bool lanes_light = lanes_ok && pl->dev.lds_bytes_tail <= 24 * 1024 && pl->W < 1024;
+    if (fixed_ok) v = AMY_VARIANT_FIXED;
+    else if (lanes_light) v = AMY_VARIANT_LANES;
+    else if (pl->W >= 4096 && g64_ok) v = AMY_VARIANT_GROUP64;
+    else if (g16_ok) v = AMY_VARIANT_GROUP16;
+    else if (g64_ok) v = AMY_VARIANT_GROUP64;
+    else if (lanes_ok) v = AMY_VARIANT_LANES;
+    else
+      return amy_fail(AMY_E_UNSUPPORTED, "window tables need %lld B of LDS even for one state per wave",
+                      (long long)(sum_l * msz));
+  }
+  pl->dev.variant = v;
+  plan_group(pl, v == AMY_VARIANT_GROUP64 ? 64 : 16);
+  if (v != AMY_VARIANT_GROUP16 && v != AMY_VARIANT_GROUP64) pl->dev.grp_g = 1;
   return AMY_OK;
 }
 
@@ -353,7 +410,8 @@ static void fill_info(const amy_problem* p, const Plan& pl, amy_info* info) {
   info->table_cache_mask = 0;
   for (int i = 0; i < p->grid.n; ++i)
     if (pl.dev.ccount[i] > 0) info->table_cache_mask |= 1 << i;
-  info->lds_bytes = pl.dev.lds_bytes;
+  info->lds_bytes = (pl.dev.grp_g > 1) ? pl.dev.lds_bytes_group
+                    : (pl.dev.variant == AMY_VARIANT_FIXED ? pl.dev.lds_bytes_fixed : pl.dev.lds_bytes);
   info->n_x = pl.dev.n_x;
   info->n_u = pl.dev.n_u;
   info->rows = pl.rows;
@@ -408,6 +466,9 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
                                   label, pk, st);
     else if (D.variant == AMY_VARIANT_FIXED)
       e = amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk,
+                                 (want_tail && k == horizon) ? tailmax : nullptr, st);
+    else if (D.grp_g > 1)
+      e = amy_launch_sweep_group(D, sk, Vb[cur], out, label, pk,
                                  (want_tail && k == horizon) ? tailmax : nullptr, st);
     else
       e = amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk,

@@ -31,3 +31,33 @@ void amy_layout(Plan* pl, int mode);
 amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl);
 amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
                        bool want_tail, Timing* tm);
+
+#include <string>
+#include <vector>
+
+// Batched launch: per-system plans, the longest-horizon-first order, the
+// tile prefix sums, the active-system counts per global step and the
+// workspace layout (tables, control block, then one region per system).
+struct BatchPlan {
+  std::vector<Plan> plans;        // input order
+  std::vector<int> order;         // launch order (horizon descending) -> input index
+  std::vector<int32_t> tprefix;   // tile prefix sums in launch order
+  std::vector<int32_t> active;    // systems still running at each global step
+  bool f64 = false;
+  int maxT = 0;
+  size_t lds = 0;                 // dynamic LDS of the launch
+  uint64_t off_sys = 0, off_tp = 0, off_act = 0, off_ctl = 0, ws_bytes = 0;
+  std::vector<uint64_t> base;     // per system (input order): its region
+};
+
+// Launch parameters of the persistent batched kernel chosen by the tuner.
+struct BatchTune {
+  int chunk = 1;          // tiles taken per work-queue grab
+  int blocks_per_cu = 0;  // resident workgroups per CU (0: as many as fit)
+  int xcd_order = 1;      // one work queue per XCD over a contiguous tile range
+};
+
+amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp);
+amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStream_t hs, char* ws,
+                         double* const* V_out, int16_t* const* policy_out, bool want_tail, const BatchTune& tune,
+                         float* ms_out);

@@ -7,7 +7,9 @@
   hipError_t amy_gen_##name##_sweep(const DevProblem&, SweepKind, const void*, void*, const uint8_t*,   \
                                     int16_t*, unsigned long long*, hipStream_t);                         \
   hipError_t amy_gen_##name##_build(const DevProblem&, bool, const uint8_t*, void*, int32_t*,           \
-                                    unsigned long long*, hipStream_t);
+                                    unsigned long long*, hipStream_t);                                   \
+  hipError_t amy_gen_##name##_group(const DevProblem&, SweepKind, const void*, void*, const uint8_t*,   \
+                                    int16_t*, unsigned long long*, hipStream_t);
 DECL_FAMILY(affine)
 DECL_FAMILY(room)
 DECL_FAMILY(unicycle)
@@ -40,6 +42,12 @@ hipError_t amy_launch_sweep_otf(const DevProblem& P, SweepKind sk, const void* V
                                 const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
                                 hipStream_t st) {
   AMY_DISPATCH(sweep, P, sk, Vin, Vout, label, pol, tailmax, st)
+}
+
+hipError_t amy_launch_sweep_group(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                                  const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                  hipStream_t st) {
+  AMY_DISPATCH(group, P, sk, Vin, Vout, label, pol, tailmax, st)
 }
 
 hipError_t amy_launch_build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,

@@ -21,6 +21,10 @@ hipError_t amy_launch_tail(const DevProblem& P, const uint8_t* label, unsigned l
 hipError_t amy_launch_sweep_otf(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
                                 const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
                                 hipStream_t st);
+// Group variant (P.grp_g lanes per state).
+hipError_t amy_launch_sweep_group(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                                  const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                  hipStream_t st);
 hipError_t amy_launch_build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,
                             unsigned long long* tailmax, hipStream_t st);
 hipError_t amy_launch_sweep_stored(const DevProblem& P, SweepKind sk, const void* T, const int32_t* org,

@@ -37,6 +37,14 @@ struct DevProblem {
   int32_t lds_bytes_tail;
   int32_t lds_bytes_fixed;    // compiled-shape sweep without the tail region
   int32_t variant;            // resolved amy_variant of the OTF sweeps
+  // Group variant (G lanes per state): 1-D tables of a state at goff[i]
+  // inside its group's LDS region of gsl entries; the innermost dimensions
+  // from index grp_nout on form the lane space split across the G lanes.
+  int32_t grp_g;
+  int32_t grp_nout;
+  int32_t gsl;
+  int32_t goff[AMY_MAXD];
+  int32_t lds_bytes_group;    // group variant: (64 / grp_g) states x gsl entries
   int64_t stride[AMY_MAXD];   // state index strides, last dimension fastest
   double lo[AMY_MAXD], h[AMY_MAXD], inv_h[AMY_MAXD];
   double inv_sigma[AMY_MAXD], xstar[AMY_MAXD];
@@ -53,3 +61,37 @@ struct DevProblem {
 };
 
 static_assert(sizeof(DevProblem) < 4096, "kernel argument limit");
+
+// ------------------------------------------------------------------ batch
+
+#define AMY_BATCH_MAX 4096       // systems per batched launch
+#define AMY_BATCH_MAX_STEPS 1024 // global steps per batched launch (max horizon)
+
+// One system of a batched launch (device copy; pointers into the workspace
+// or the caller's outputs).
+struct BatchSys {
+  DevProblem P;                  // plan, variant LANES
+  uint8_t* label;
+  void* V0;                      // working-precision ping-pong
+  void* V1;
+  double* Vout;                  // FP64 V at k = 1 (caller's buffer)
+  int16_t* pol;                  // caller's policy (T_d * n_x) or null
+  unsigned long long* tailmax;   // FP64 max row tail (bits)
+  void* T;                       // stored rows (mode STORED) or null
+  int32_t* org;
+  int32_t horizon;
+  int32_t tiles;                 // 64-state tiles
+  int32_t mode;                  // AMY_MODE_STORED / AMY_MODE_OTF
+  int32_t want_tail;
+  int32_t step_base;             // server: global step at which the system's step T_d runs
+  int32_t pad[3];
+};
+
+// Control words of a batched launch (zeroed before the launch).
+struct BatchCtl {
+  unsigned bar_count;            // grid barrier arrivals
+  unsigned bar_gen;              // grid barrier generation
+  unsigned err;                  // 1: a barrier wait gave up
+  unsigned pad;
+  unsigned ctr[(AMY_BATCH_MAX_STEPS + 1) * 8];  // work-queue counters [phase][XCD] (phase 0 = init)
+};

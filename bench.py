@@ -152,12 +152,108 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _serve_run(srv, reqs, times):
+    """Submit reqs at the given offsets (s) and collect every result on a
+    waiter thread; returns (wall_s, per-request latencies in ms, rows)."""
+    import threading
+    tickets, lat, err = [None] * len(reqs), [0.0] * len(reqs), []
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(len(reqs)):
+            ready.acquire()
+            try:
+                _, _, info = srv.wait(tickets[i], timeout_ms=-1)
+                lat[i] = info["t_total_ms"]
+            except Exception as e:  # noqa: BLE001 - reported below
+                err.append(f"{reqs[i].name}: {e}")
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for i, (p, t) in enumerate(zip(reqs, times)):
+        d = t0 + t - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        tickets[i] = srv.submit(p)
+        ready.release()
+    th.join()
+    wall = time.perf_counter() - t0
+    if err:
+        raise RuntimeError("serving requests failed: " + "; ".join(err[:3]))
+    return wall, lat
+
+
+def bench_serve(args):
+    """The serving stream: Poisson arrivals of FP32 solve requests (2-D
+    linear, 3-D unicycle and 5-D room families with log-uniform state counts
+    in [1e3, 2e6], plus 7-D vehicles at 2.1e6 states for 10%) into the
+    continuous-batching server.  Capacity is measured closed-loop (all
+    requests queued at once); the stream is then replayed open-loop at 0.5
+    and 0.8 of that capacity.  value = row-updates/s at load 0.8."""
+    import numpy as np
+    import torch
+
+    import paper_2005_06191_amd as A
+    torch.cuda.set_device(0)
+    n = args.requests
+    stream = W.serving_stream(count=3 * n + 8)
+    reqs = [p for _, p in stream]
+    warm, cap_set = reqs[:8], reqs[8:8 + n]
+    gaps = np.diff([0.0] + [t for t, _ in stream[8 + n:]])
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    out_loads = []
+    with A.Server(hbm_budget_bytes=budget, max_slots=args.slots) as srv:
+        _serve_run(srv, warm, [0.0] * len(warm))
+        srv.reset_stats()
+        wall, lat = _serve_run(srv, cap_set, [0.0] * n)
+        st_cap = srv.stats()
+        work = sum(p.rows * p.horizon for p in cap_set)
+        cap_qps = n / wall
+        cap = {"requests": n, "wall_s": wall, "qps": cap_qps, "row_updates_per_s": work / wall,
+               "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
+               "max_active": st_cap["max_active"], "hbm_peak_gb": st_cap["hbm_peak"] / 2 ** 30}
+        for k, rho in enumerate((0.5, 0.8)):
+            sub = reqs[8 + n + k * n: 8 + n + (k + 1) * n]
+            g = gaps[k * n:(k + 1) * n]
+            # rescale the stream's exponential gaps to the target rate
+            times = np.cumsum(g / g.mean() / (rho * cap_qps)) - g[0] / g.mean() / (rho * cap_qps)
+            srv.reset_stats()
+            wall, lat = _serve_run(srv, sub, times.tolist())
+            st = srv.stats()
+            w = sum(p.rows * p.horizon for p in sub)
+            out_loads.append({"load": rho, "offered_qps": rho * cap_qps, "requests": n, "wall_s": wall,
+                              "row_updates_per_s": w / wall, "p50_ms": percentile(lat, 0.5),
+                              "p99_ms": percentile(lat, 0.99), "mean_ms": statistics.mean(lat),
+                              "max_active": st["max_active"], "steps": st["steps"],
+                              "busy_frac": st["busy_s"] / wall})
+    hi = out_loads[-1]
+    fams = {}
+    for p in reqs[8:8 + 3 * n]:
+        fams[p.name.split("-")[1]] = fams.get(p.name.split("-")[1], 0) + 1
+    out = {
+        "metric": "Bellman (state,input) row-updates/sec FP32 vs FP64 at <=1e-5 err; p50/p99",
+        "value": hi["row_updates_per_s"], "unit": "row-updates/s", "n_gpus": 1, "steps": n,
+        "warmup": len(warm), "ms_per_step": 1e3 * hi["wall_s"] / n, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving stream: Poisson arrivals of FP32 requests, families 2-D/3-D/5-D "
+                               "(n_x logU[1e3,2e6]) + 10% 7-D vehicle (2.1e6 states); value at load 0.8",
+                   "families": fams, "hbm_budget_gb": args.hbm_budget_gb, "max_slots": args.slots},
+        "p50_ms": hi["p50_ms"], "p99_ms": hi["p99_ms"],
+        "serve": {"capacity": cap, "loads": out_loads},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS) + ["batch64"])
+    ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--requests", type=int, default=120, help="serve: requests per measured phase")
+    ap.add_argument("--slots", type=int, default=64, help="serve: requests on the device at once")
+    ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: device arena")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--mode", default="otf", choices=["otf", "stored"])
     ap.add_argument("--variant", default="auto", choices=["auto", "lanes", "fixed"])
@@ -171,6 +267,9 @@ def main():
 
     if args.workload == "batch64":
         bench_batch(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     import torch

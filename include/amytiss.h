@@ -242,6 +242,54 @@ amy_status amy_tune_load(const char* path);
 amy_status amy_tune_clear(void);
 int32_t amy_tune_entries(void);
 
+/* ----------------------------------------------------------------- server
+ * Request loop with continuous batching.  A worker thread owns one HIP
+ * stream and one device arena of hbm_budget_bytes (the only device
+ * allocation, made here).  Requests are admitted in arrival order while a
+ * slot (max_slots) and arena space for their footprint are free; each
+ * request's mode (stored rows vs on the fly) is picked by memory and a
+ * cost model when its mode is AUTO.  Every iteration advances all admitted
+ * requests by one Bellman step in a single replay of a captured graph, so
+ * requests that arrive while others run join at the next step and their
+ * work overlaps on the device; finished requests leave, freeing their slot
+ * and memory.  A request's result is bitwise equal to amy_solve of the same
+ * problem with the variant its info reports (LANES or GROUP*).
+ * Supported: the dynamics families of amy_batch_solve. */
+typedef struct amy_server amy_server;
+typedef struct {
+  uint64_t hbm_budget_bytes;     /* device arena (>= 1 MiB)                  */
+  int32_t max_slots;             /* requests on the device at once (1..4096) */
+  int32_t device;                /* HIP device ordinal                       */
+} amy_server_cfg;
+
+typedef struct {
+  uint64_t submitted, completed, failed;
+  int32_t queued, active, max_active;
+  uint64_t hbm_in_use, hbm_peak;
+  uint64_t steps;                /* batched step launches (graph replays)    */
+  double row_updates;            /* completed requests' n_x n_u T_d          */
+  double busy_s;                 /* worker time with work on the device      */
+  double p50_ms, p99_ms, mean_ms;/* submit-to-result latency, completed      */
+} amy_server_stats;
+
+amy_status amy_server_create(const amy_server_cfg* cfg, amy_server** out);
+/* Copies the problem; want_policy != 0 keeps the T_d x n_x policy. */
+amy_status amy_server_submit(amy_server* s, const amy_problem* p, int32_t want_policy, uint64_t* ticket);
+/* Result of a finished request into host buffers (V_host: n_x doubles;
+ * policy_host: T_d * n_x int16 or NULL); the ticket is then released.
+ * info: mode, variant, tail bound; t_build_ms = queueing time,
+ * t_sweeps_ms = time admitted, t_total_ms = latency.
+ * poll: AMY_E_NOTREADY while running.  wait: blocks up to timeout_ms
+ * (< 0: no limit) before answering AMY_E_NOTREADY. */
+amy_status amy_server_poll(amy_server* s, uint64_t ticket, double* V_host, int16_t* policy_host,
+                           amy_info* info);
+amy_status amy_server_wait(amy_server* s, uint64_t ticket, int32_t timeout_ms, double* V_host,
+                           int16_t* policy_host, amy_info* info);
+amy_status amy_server_get_stats(amy_server* s, amy_server_stats* out);
+amy_status amy_server_reset_stats(amy_server* s);
+/* Finishes the admitted requests, drops the queued ones, frees everything. */
+amy_status amy_server_destroy(amy_server* s);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* amy_last_error(void);
 

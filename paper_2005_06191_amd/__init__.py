@@ -5,9 +5,9 @@ reach-avoid), stored or on-the-fly, behind the C ABI of include/amytiss.h.
 The compute runs in libamytiss_hip.so (hand-written HIP for gfx950);
 ``binding`` marshals arguments and allocates device memory with PyTorch.
 """
-from .binding import (AmyError, BatchSolver, Result, Solver, batch_query, batch_solve,  # noqa: F401
+from .binding import (AmyError, BatchSolver, Result, Server, Solver, batch_query, batch_solve,  # noqa: F401
                       query, solve, tune_clear, tune_entries, tune_load, tune_save, tune_solve,
                       version)
 
-__all__ = ["AmyError", "BatchSolver", "Result", "Solver", "batch_query", "batch_solve", "query",
+__all__ = ["AmyError", "BatchSolver", "Result", "Server", "Solver", "batch_query", "batch_solve", "query",
            "solve", "tune_clear", "tune_entries", "tune_load", "tune_save", "tune_solve", "version"]

@@ -84,6 +84,21 @@ class TuneResult(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerCfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_slots", C.c_int32), ("device", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("queued", C.c_int32), ("active", C.c_int32), ("max_active", C.c_int32),
+                ("hbm_in_use", C.c_uint64), ("hbm_peak", C.c_uint64), ("steps", C.c_uint64),
+                ("row_updates", C.c_double), ("busy_s", C.c_double), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("mean_ms", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class AmyError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"amytiss {STATUS.get(status, status)}: {msg}")
@@ -122,6 +137,17 @@ def lib():
             getattr(L, fn).restype = C.c_int
         L.amy_tune_clear.restype = C.c_int
         L.amy_tune_entries.restype = C.c_int32
+        sp = C.c_void_p
+        L.amy_server_create.argtypes = [C.POINTER(ServerCfg), C.POINTER(sp)]
+        L.amy_server_submit.argtypes = [sp, pp, C.c_int32, C.POINTER(C.c_uint64)]
+        L.amy_server_wait.argtypes = [sp, C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p, ip]
+        L.amy_server_poll.argtypes = [sp, C.c_uint64, C.c_void_p, C.c_void_p, ip]
+        L.amy_server_get_stats.argtypes = [sp, C.POINTER(ServerStats)]
+        L.amy_server_reset_stats.argtypes = [sp]
+        L.amy_server_destroy.argtypes = [sp]
+        for fn in ("amy_server_create", "amy_server_submit", "amy_server_wait", "amy_server_poll",
+                   "amy_server_get_stats", "amy_server_reset_stats", "amy_server_destroy"):
+            getattr(L, fn).restype = C.c_int
         L.amy_last_error.restype = C.c_char_p
         L.amy_version.restype = C.c_char_p
         _lib = L
@@ -312,3 +338,69 @@ def tune_clear():
 
 def tune_entries() -> int:
     return int(lib().amy_tune_entries())
+
+
+# ----------------------------------------------------------------- server
+
+class Server:
+    """Request loop with continuous batching (amy_server_* of the C ABI).
+    Results come back in host memory (numpy)."""
+
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, max_slots: int = 64, device: int = 0):
+        cfg = ServerCfg(int(hbm_budget_bytes), int(max_slots), int(device))
+        self._h = C.c_void_p()
+        check(lib().amy_server_create(C.byref(cfg), C.byref(self._h)))
+        self._meta = {}
+
+    def submit(self, p, want_policy: bool = False, **kw) -> int:
+        s = to_struct(p, **kw)
+        t = C.c_uint64()
+        check(lib().amy_server_submit(self._h, C.byref(s), int(want_policy), C.byref(t)))
+        self._meta[t.value] = (p.n_x, p.horizon, want_policy)
+        return int(t.value)
+
+    def _collect(self, fn, ticket, *extra):
+        import numpy as np
+        n_x, T, want_pol = self._meta[ticket]
+        V = np.empty(n_x, np.float64)
+        pol = np.empty((T, n_x), np.int16) if (want_pol and T > 0) else None
+        inf = Info()
+        rc = fn(self._h, C.c_uint64(ticket), *extra, C.c_void_p(V.ctypes.data),
+                C.c_void_p(pol.ctypes.data) if pol is not None else None, C.byref(inf))
+        if rc == E_NOTREADY:
+            return None
+        del self._meta[ticket]
+        check(rc)
+        return V, pol, inf.as_dict()
+
+    def poll(self, ticket: int):
+        """(V, policy, info) when finished, else None."""
+        return self._collect(lib().amy_server_poll, ticket)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        return self._collect(lib().amy_server_wait, ticket, C.c_int32(int(timeout_ms)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(lib().amy_server_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def reset_stats(self):
+        check(lib().amy_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h:
+            check(lib().amy_server_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

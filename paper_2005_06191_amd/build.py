@@ -19,7 +19,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["amy_kernels.hip", "amy_gen_affine.hip", "amy_gen_room.hip", "amy_gen_misc.hip",
-           "amy_fixed.hip", "amy_batch.hip", "amy_host.cpp", "amy_batch_host.cpp", "amy_tune.cpp"]
+           "amy_fixed.hip", "amy_batch.hip", "amy_host.cpp", "amy_batch_host.cpp", "amy_tune.cpp",
+           "amy_server.cpp"]
 
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

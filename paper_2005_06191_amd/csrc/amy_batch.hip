@@ -249,12 +249,17 @@ __global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_e
   }
 }
 
-// One step of every listed system; BatchSys::step_base holds the system's
-// local step t for this launch (written by the host before each replay).
+// One step of every system of a table (the serving loop's captured step).
+// meta[0] = number of systems, meta[1 ..] = their tile prefix sums;
+// BatchSys::step_base holds each system's local step t for this launch.
+// Both are read from device memory, so one captured launch serves any set
+// of active systems.  Items are dealt by a fixed stride (no counters).
 template <bool F64>
-__global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) k_batch_step(const BatchSys* __restrict__ sys, int nsys,
-                                                            const int32_t* __restrict__ tprefix) {
+__global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8)))
+k_batch_step(const BatchSys* __restrict__ sys, const int32_t* __restrict__ meta) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int nsys = meta[0];
+  const int32_t* tprefix = meta + 1;
   const uint32_t nitems = (uint32_t)tprefix[nsys];
   for (uint32_t it = xcd_block(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
     const int j = find_sys(tprefix, nsys, it);
@@ -294,10 +299,14 @@ hipError_t amy_launch_batch_persistent(bool f64, unsigned grid, size_t lds, cons
                                     (unsigned)lds, st);
 }
 
-hipError_t amy_launch_batch_step(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
-                                 const int32_t* tprefix, hipStream_t st) {
-  if (f64) hipLaunchKernelGGL((k_batch_step<true>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, nsys, tprefix);
-  else hipLaunchKernelGGL((k_batch_step<false>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, nsys, tprefix);
+const void* amy_batch_step_kernel(bool f64) {
+  return f64 ? (const void*)&k_batch_step<true> : (const void*)&k_batch_step<false>;
+}
+
+hipError_t amy_launch_batch_step(bool f64, unsigned grid, size_t lds, const BatchSys* sys, const int32_t* meta,
+                                 hipStream_t st) {
+  if (f64) hipLaunchKernelGGL((k_batch_step<true>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, meta);
+  else hipLaunchKernelGGL((k_batch_step<false>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, meta);
   return hipGetLastError();
 }
 

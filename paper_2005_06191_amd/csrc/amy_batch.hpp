@@ -11,8 +11,10 @@ const void* amy_batch_persistent_kernel(bool f64);
 hipError_t amy_launch_batch_persistent(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
                                        const int32_t* tprefix, const int32_t* active, int max_steps,
                                        BatchCtl* ctl, int chunk, int xcd_order, hipStream_t st);
-hipError_t amy_launch_batch_step(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
-                                 const int32_t* tprefix, hipStream_t st);
+const void* amy_batch_step_kernel(bool f64);
+// meta[0] = number of systems, meta[1..] = tile prefix sums (device memory)
+hipError_t amy_launch_batch_step(bool f64, unsigned grid, size_t lds, const BatchSys* sys, const int32_t* meta,
+                                 hipStream_t st);
 hipError_t amy_launch_batch_init(bool f64, const BatchSys* sys, int nsys, const int32_t* tprefix, unsigned grid,
                                  hipStream_t st);
 hipError_t amy_launch_fill_u32(unsigned* p, size_t n, hipStream_t st);

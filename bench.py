@@ -31,6 +31,33 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64, published
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, published
 C_ERFC = 20                  # flops charged per 1-D erfc evaluation
 
+# HBM bytes per launch of the dominant sweep, from two profiler counter
+# passes (FETCH_SIZE, WRITE_SIZE) scaled by what the same counters read for a
+# 1 GiB device copy (x2.000 and x1.000); recorded with a hash of the kernel's
+# sources and reported only while the sources still hash to it.
+TRAFFIC = {
+    ("unicycle3d", "otf", "fixed"): {"read": 4.124e6, "write": 3.600e6, "sha": "6813f0ca33ac1f3e",
+                                     "sources": ("amy_fixed.hip", "amy_device.hpp", "amy_plan.hpp")},
+    ("unicycle3d", "stored", "fixed"): {"read": 5.126e9, "write": 3.600e6, "sha": "363d06f2a877b165",
+                                        "sources": ("amy_generic.hpp", "amy_device.hpp", "amy_plan.hpp",
+                                                    "amy_kernels.hip")},
+}
+
+
+def traffic_for(workload, mode, variant):
+    import hashlib
+    t = TRAFFIC.get((workload, mode, variant))
+    if t is None:
+        return None
+    h = hashlib.sha256()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_2005_06191_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != t["sha"]:
+        return None
+    return t["read"] + t["write"]
+
+
 WORKLOADS = {
     "unicycle3d": lambda prec, mode: W.unicycle3d(precision=prec, mode=mode),
     "room5d": lambda prec, mode: W.room5d(precision=prec, mode=mode),
@@ -152,12 +179,29 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def _serve_run(srv, reqs, times):
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size (reads and writes mib MiB
+    each), for scaling the HBM fetch/write counters of a profiler run."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(10):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "launches": 10}), flush=True)
+
+
+def _serve_run(srv, reqs, times, phase=""):
     """Submit reqs at the given offsets (s) and collect every result on a
-    waiter thread; returns (wall_s, per-request latencies in ms, rows)."""
+    waiter thread; returns (wall_s, per-request latencies in ms).  Progress
+    goes to stderr every 10 results."""
     import threading
     tickets, lat, err = [None] * len(reqs), [0.0] * len(reqs), []
     ready = threading.Semaphore(0)
+    t_start = time.perf_counter()
 
     def waiter():
         for i in range(len(reqs)):
@@ -167,6 +211,9 @@ def _serve_run(srv, reqs, times):
                 lat[i] = info["t_total_ms"]
             except Exception as e:  # noqa: BLE001 - reported below
                 err.append(f"{reqs[i].name}: {e}")
+            if (i + 1) % 10 == 0 or i + 1 == len(reqs):
+                print(f"[serve] {phase}: {i + 1}/{len(reqs)} done at {time.perf_counter() - t_start:.1f} s",
+                      file=sys.stderr, flush=True)
 
     th = threading.Thread(target=waiter)
     th.start()
@@ -188,59 +235,59 @@ def bench_serve(args):
     """The serving stream: Poisson arrivals of FP32 solve requests (2-D
     linear, 3-D unicycle and 5-D room families with log-uniform state counts
     in [1e3, 2e6], plus 7-D vehicles at 2.1e6 states for 10%) into the
-    continuous-batching server.  Capacity is measured closed-loop (all
-    requests queued at once); the stream is then replayed open-loop at 0.5
-    and 0.8 of that capacity.  value = row-updates/s at load 0.8."""
+    continuous-batching server.  One request set is replayed three times:
+    closed-loop (all queued at once) for the capacity, then open-loop with the
+    stream's exponential gaps rescaled to 0.5 and 0.8 of that capacity.
+    value = row-updates/s at load 0.8."""
     import numpy as np
     import torch
 
     import paper_2005_06191_amd as A
     torch.cuda.set_device(0)
-    n = args.requests
-    stream = W.serving_stream(count=3 * n + 8)
-    reqs = [p for _, p in stream]
-    warm, cap_set = reqs[:8], reqs[8:8 + n]
-    gaps = np.diff([0.0] + [t for t, _ in stream[8 + n:]])
+    n, n_warm = args.requests, 10
+    stream = W.serving_stream(count=n + n_warm)
+    warm = [p for _, p in stream[:n_warm]]
+    sample = [p for _, p in stream[n_warm:]]
+    gaps = np.diff([stream[n_warm - 1][0]] + [t for t, _ in stream[n_warm:]])
+    work = sum(p.rows * p.horizon for p in sample)
     budget = int(args.hbm_budget_gb * (1 << 30))
-    out_loads = []
+    loads = []
     with A.Server(hbm_budget_bytes=budget, max_slots=args.slots) as srv:
-        _serve_run(srv, warm, [0.0] * len(warm))
+        _serve_run(srv, warm, [0.0] * len(warm), "warm-up")
         srv.reset_stats()
-        wall, lat = _serve_run(srv, cap_set, [0.0] * n)
-        st_cap = srv.stats()
-        work = sum(p.rows * p.horizon for p in cap_set)
+        wall, lat = _serve_run(srv, sample, [0.0] * n, "capacity")
+        st = srv.stats()
         cap_qps = n / wall
-        cap = {"requests": n, "wall_s": wall, "qps": cap_qps, "row_updates_per_s": work / wall,
+        cap = {"wall_s": wall, "qps": cap_qps, "row_updates_per_s": work / wall,
                "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
-               "max_active": st_cap["max_active"], "hbm_peak_gb": st_cap["hbm_peak"] / 2 ** 30}
-        for k, rho in enumerate((0.5, 0.8)):
-            sub = reqs[8 + n + k * n: 8 + n + (k + 1) * n]
-            g = gaps[k * n:(k + 1) * n]
-            # rescale the stream's exponential gaps to the target rate
-            times = np.cumsum(g / g.mean() / (rho * cap_qps)) - g[0] / g.mean() / (rho * cap_qps)
+               "max_active": st["max_active"], "hbm_peak_gb": st["hbm_peak"] / 2 ** 30}
+        for rho in (0.5, 0.8):
+            times = np.cumsum(gaps) - gaps[0]
+            times = times / times[-1] * (n - 1) / (rho * cap_qps) if n > 1 else times
             srv.reset_stats()
-            wall, lat = _serve_run(srv, sub, times.tolist())
+            wall, lat = _serve_run(srv, sample, times.tolist(), f"load {rho}")
             st = srv.stats()
-            w = sum(p.rows * p.horizon for p in sub)
-            out_loads.append({"load": rho, "offered_qps": rho * cap_qps, "requests": n, "wall_s": wall,
-                              "row_updates_per_s": w / wall, "p50_ms": percentile(lat, 0.5),
-                              "p99_ms": percentile(lat, 0.99), "mean_ms": statistics.mean(lat),
-                              "max_active": st["max_active"], "steps": st["steps"],
-                              "busy_frac": st["busy_s"] / wall})
-    hi = out_loads[-1]
+            loads.append({"load": rho, "offered_qps": rho * cap_qps, "wall_s": wall,
+                          "row_updates_per_s": work / wall, "p50_ms": percentile(lat, 0.5),
+                          "p99_ms": percentile(lat, 0.99), "mean_ms": statistics.mean(lat),
+                          "max_active": st["max_active"], "steps": st["steps"],
+                          "busy_frac": st["busy_s"] / wall})
+    hi = loads[-1]
     fams = {}
-    for p in reqs[8:8 + 3 * n]:
-        fams[p.name.split("-")[1]] = fams.get(p.name.split("-")[1], 0) + 1
+    for p in sample:
+        f = p.name.split("-")[1]
+        fams[f] = fams.get(f, 0) + 1
     out = {
         "metric": "Bellman (state,input) row-updates/sec FP32 vs FP64 at <=1e-5 err; p50/p99",
         "value": hi["row_updates_per_s"], "unit": "row-updates/s", "n_gpus": 1, "steps": n,
-        "warmup": len(warm), "ms_per_step": 1e3 * hi["wall_s"] / n, "higher_is_better": True,
+        "warmup": n_warm, "ms_per_step": 1e3 * hi["wall_s"] / n, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "serving stream: Poisson arrivals of FP32 requests, families 2-D/3-D/5-D "
                                "(n_x logU[1e3,2e6]) + 10% 7-D vehicle (2.1e6 states); value at load 0.8",
-                   "families": fams, "hbm_budget_gb": args.hbm_budget_gb, "max_slots": args.slots},
+                   "requests": n, "row_updates": work, "families": fams,
+                   "hbm_budget_gb": args.hbm_budget_gb, "max_slots": args.slots},
         "p50_ms": hi["p50_ms"], "p99_ms": hi["p99_ms"],
-        "serve": {"capacity": cap, "loads": out_loads},
+        "serve": {"capacity": cap, "loads": loads},
     }
     print(json.dumps(out), flush=True)
 
@@ -251,12 +298,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS) + ["batch64", "serve"])
-    ap.add_argument("--requests", type=int, default=120, help="serve: requests per measured phase")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests in the measured set")
     ap.add_argument("--slots", type=int, default=64, help="serve: requests on the device at once")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: device arena")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--mode", default="otf", choices=["otf", "stored"])
-    ap.add_argument("--variant", default="auto", choices=["auto", "lanes", "fixed"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "lanes", "fixed", "group16", "group64"])
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="only run a plain device copy of this size 10 times (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     args = ap.parse_args()
@@ -265,6 +314,9 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calib_mib > 0:
+        copy_calibration(args.copy_calib_mib)
+        return
     if args.workload == "batch64":
         bench_batch(args)
         return
@@ -293,14 +345,16 @@ def main():
         fl = algorithmic_flops_per_row(plan)
         achieved = fl * rows / (sweep_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "k_sweep_otf (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic_for(args.workload, args.mode, plan["variant"]),
+                "kernel": f"sweep {plan['variant']} (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
                 "flops_per_row": fl, "rows_per_launch": rows}
     else:
         by = stored_bytes_per_row(plan, False)
         achieved = by * rows / (sweep_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic_for(args.workload, args.mode, plan["variant"]),
                 "kernel": "k_sweep_stored (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
                 "bytes_per_row": by, "rows_per_launch": rows}
 

@@ -18,6 +18,11 @@
  * Everything is FP64.  Every cell probability is computed directly as a
  * product of 1-D normal-CDF differences (glibc erf/erfc); no table is shared
  * between cells.
+ *
+ * Parity unpinned: the unicycle, room-ring and 7-D vehicle mean functions
+ * are model definitions checked only against a second transcription (the
+ * 7-D vehicle's printed formulas may also be garbled); the affine family is
+ * pinned by the separable-product identity and the one-step closed form.
  */
 #ifndef AMY_ORACLE_H
 #define AMY_ORACLE_H

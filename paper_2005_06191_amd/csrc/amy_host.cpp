@@ -432,6 +432,29 @@ extern "C" amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_in
 
 // ------------------------------------------------------------------ solve
 
+// Bellman step k (T_d >= k >= 1, Alg. 4's time loop) of a solve whose
+// labels and V_{T_d+1} (and stored rows) are in place: reads V buffer
+// (T_d - k) & 1 and writes the other one, or V_out at k = 1.
+hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
+                            int k, bool want_tail) {
+  const DevProblem& D = pl.dev;
+  char* base = (char*)ws;
+  const uint8_t* label = (const uint8_t*)(base + pl.off_label);
+  void* Vb[2] = {base + pl.off_v0, base + pl.off_v1};
+  unsigned long long* tail = (want_tail && k == horizon) ? (unsigned long long*)(base + pl.off_tail) : nullptr;
+  const int cur = (horizon - k) & 1;
+  const bool last = (k == 1);
+  const SweepKind sk = pl.f64 ? SWEEP_F64 : (last ? SWEEP_F32_LAST : SWEEP_F32);
+  void* out = last ? (void*)V_out : Vb[cur ^ 1];
+  int16_t* pk = pol ? pol + (int64_t)(k - 1) * D.n_x : nullptr;
+  if (pl.mode == AMY_MODE_STORED)
+    return amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
+                                   label, pk, st);
+  if (D.variant == AMY_VARIANT_FIXED) return amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk, tail, st);
+  if (D.grp_g > 1) return amy_launch_sweep_group(D, sk, Vb[cur], out, label, pk, tail, st);
+  return amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk, tail, st);
+}
+
 amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol,
                        int horizon, bool want_tail, Timing* tm) {
   const DevProblem& D = pl.dev;
@@ -454,27 +477,10 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
       return amy_hip_fail(e, "build kernel");
   }
   if (tm) hipEventRecord(tm->ev[1], st);
-  int cur = 0;
   for (int k = horizon; k >= 1; --k) {
-    const bool last = (k == 1);
-    if (tm && last) hipEventRecord(tm->ev[2], st);
-    const SweepKind sk = pl.f64 ? SWEEP_F64 : (last ? SWEEP_F32_LAST : SWEEP_F32);
-    void* out = last ? (void*)V_out : Vb[cur ^ 1];
-    int16_t* pk = pol ? pol + (int64_t)(k - 1) * D.n_x : nullptr;
-    if (stored)
-      e = amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
-                                  label, pk, st);
-    else if (D.variant == AMY_VARIANT_FIXED)
-      e = amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk,
-                                 (want_tail && k == horizon) ? tailmax : nullptr, st);
-    else if (D.grp_g > 1)
-      e = amy_launch_sweep_group(D, sk, Vb[cur], out, label, pk,
-                                 (want_tail && k == horizon) ? tailmax : nullptr, st);
-    else
-      e = amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk,
-                               (want_tail && k == horizon) ? tailmax : nullptr, st);
-    if (e != hipSuccess) return amy_hip_fail(e, "sweep kernel");
-    cur ^= 1;
+    if (tm && k == 1) hipEventRecord(tm->ev[2], st);
+    if ((e = amy_enqueue_step(pl, st, ws, V_out, pol, horizon, k, want_tail)) != hipSuccess)
+      return amy_hip_fail(e, "sweep kernel");
   }
   if (tm) {
     if (horizon == 0) hipEventRecord(tm->ev[2], st);

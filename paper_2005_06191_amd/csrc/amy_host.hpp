@@ -31,6 +31,8 @@ void amy_layout(Plan* pl, int mode);
 amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl);
 amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
                        bool want_tail, Timing* tm);
+hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
+                            int k, bool want_tail);
 
 #include <string>
 #include <vector>

@@ -8,15 +8,20 @@
 //      request by memory and a cost model;
 //   2. starts the newly admitted requests (labels / terminal values; the
 //      stored rows of Alg. 2 for stored requests);
-//   3. advances EVERY active request by one Bellman step with a single
-//      replay of a captured graph (table upload + one batched step kernel
-//      reading the slot table from device memory), so requests that arrive
-//      while others run join at the next step boundary and their work
-//      overlaps on the device;
+//   3. advances EVERY active request by one Bellman step: small requests
+//      share a single replay of a captured graph (table upload + one
+//      batched step kernel reading the slot table from device memory);
+//      a request that fills the chip by itself (>= SOLO_STATES states) or
+//      whose family the batched kernel lacks gets its own sweep launch for
+//      the step, using the single-system kernel chosen for it (the
+//      compiled-shape sweep where one matches).  Requests that arrive while
+//      others run join at the next step boundary and their work overlaps
+//      on the device;
 //   4. retires finished requests (result copied to host memory, arena space
 //      and slot freed).
 // A request's rows are computed by the same per-state code whatever it is
-// batched with, so its result equals a lone solve bit for bit.
+// batched with, so its result equals a lone solve with the sweep variant
+// its info reports, bit for bit.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -101,6 +106,7 @@ struct Request {
   uint64_t off = 0, bytes = 0, off_v = 0, off_pol = 0;
   int t = 0;  // local step (0 = the step k = T_d)
   bool want_policy = false;
+  bool solo = false;  // own sweep launch per step instead of the batched one
   std::vector<double> V;
   std::vector<int16_t> pol;
   double max_tail = 0;
@@ -110,6 +116,8 @@ struct Request {
 // stored rows only where streaming them beats recomputing them.
 const double R_ALU = 2.0e13;  // achieved algorithmic flop/s of the OTF sweep
 const double R_HBM = 4.0e12;  // achieved byte/s of the stored sweep
+// 1024 tiles of 64 states: enough work for one launch to fill the chip
+const int64_t SOLO_STATES = 65536;
 double cost_otf(const Plan& pl, int T) {
   double edges = 0;
   for (int i = 0; i < pl.dev.n; ++i) edges += pl.dev.L[i] + 1;
@@ -184,6 +192,7 @@ amy_status amy_server::step_graph(int prec, int tier, hipGraphExec_t* out) {
 }
 
 void amy_server::fail_active(const char* what, hipError_t e) {
+  (void)hipStreamSynchronize(stream);  // nothing may still use the arena blocks
   std::lock_guard<std::mutex> g(mu);
   for (Request* r : active) {
     r->state = RQ_FAILED;
@@ -278,7 +287,7 @@ void amy_server::run() {
       int32_t* meta = h_meta[prec];
       meta[1] = 0;
       for (Request* r : act) {
-        if ((int)r->plan.f64 != prec || r->t >= r->prob.horizon) continue;
+        if (r->solo || (int)r->plan.f64 != prec || r->t >= r->prob.horizon) continue;
         const Plan& pl = r->plan;
         char* b = arena_base + r->off;
         BatchSys& B = h_sys[prec][n];
@@ -316,18 +325,24 @@ void amy_server::run() {
         ok = false;
         break;
       }
+      // the replay reads the pinned tables; they are rewritten only after
+      // the stream synchronisation at the end of this iteration
       hipError_t e = hipGraphLaunch(ex, stream);
       if (e != hipSuccess) {
         fail_active("server step launch", e);
         ok = false;
         break;
       }
-      // the pinned tables are read by the replay: wait before reuse
-      e = hipStreamSynchronize(stream);
+    }
+    for (Request* r : act) {
+      if (!ok || !r->solo || r->t >= r->prob.horizon) continue;
+      char* b = arena_base + r->off;
+      hipError_t e = amy_enqueue_step(r->plan, stream, b, (double*)(b + r->off_v),
+                                      r->want_policy ? (int16_t*)(b + r->off_pol) : nullptr, r->prob.horizon,
+                                      r->prob.horizon - r->t, r->plan.mode != AMY_MODE_STORED);
       if (e != hipSuccess) {
-        fail_active("server step", e);
+        fail_active("server solo step", e);
         ok = false;
-        break;
       }
     }
     if (!ok) continue;
@@ -408,7 +423,6 @@ extern "C" amy_status amy_server_submit(amy_server* s, const amy_problem* p, int
   // mode by memory and cost: stored rows only if they fit in half the
   // arena and streaming them is estimated cheaper than recomputing
   amy_problem q = *p;
-  if (q.variant == AMY_VARIANT_FIXED) q.variant = AMY_VARIANT_LANES;
   int mode = p->mode;
   if (mode == AMY_MODE_AUTO) {
     Plan ps, po;
@@ -433,12 +447,11 @@ extern "C" amy_status amy_server_submit(amy_server* s, const amy_problem* p, int
     delete r;
     return st;
   }
-  if (!amy_batch_supports(r->plan.dev.kind, r->plan.dev.n, r->plan.mode)) {
-    delete r;
-    return amy_fail(AMY_E_UNSUPPORTED, "dynamics kind %d with n=%d (%s) is not compiled into the step kernel",
-                    p->dyn.kind, p->grid.n, r->plan.mode == AMY_MODE_STORED ? "stored" : "otf");
-  }
-  if (r->plan.dev.variant == AMY_VARIANT_FIXED) r->plan.dev.variant = AMY_VARIANT_LANES;
+  // large requests, and families the batched kernel lacks, take their own
+  // launch per step; the rest share the batched step, which runs the
+  // run-time-window code (same bits as the compiled-shape sweep)
+  r->solo = r->plan.dev.n_x >= SOLO_STATES || !amy_batch_supports(r->plan.dev.kind, r->plan.dev.n, r->plan.mode);
+  if (!r->solo && r->plan.dev.variant == AMY_VARIANT_FIXED) r->plan.dev.variant = AMY_VARIANT_LANES;
   r->off_v = al256(r->plan.ws_bytes);
   r->off_pol = al256(r->off_v + (uint64_t)r->plan.dev.n_x * 8);
   r->bytes = r->off_pol + (r->want_policy ? al256((uint64_t)p->horizon * r->plan.dev.n_x * 2) : 0);

@@ -37,7 +37,19 @@ def _mix():
     ps.append(W.room5d(cells=6, n=3, precision="fp64", mode="otf", horizon=5).with_(name="room3-f64"))
     ps.append(_wide_window())
     ps.append(W.linear2d(cells=20, precision="fp32", mode="otf", horizon=0).with_(name="lin-T0"))
+    # large enough for its own launch per step (compiled-shape sweep)
+    ps.append(W.scaled_family(W.unicycle3d(horizon=3), 7.0e4).with_(name="uni-solo"))
+    # a family the batched kernel lacks: own launch per step as well
+    ps.append(_affine5())
     return ps
+
+
+def _affine5():
+    lo, h, cnt = W.tiling((-1.0,) * 5, (1.0,) * 5, (4,) * 5)
+    A5 = np.eye(5) * 0.6 + np.eye(5, k=1) * 0.1
+    B5 = np.array([[0.0], [0.0], [0.0], [0.0], [1.0]])
+    return W.linear2d(precision="fp32", mode="otf", horizon=4).with_(
+        lo=lo, h=h, count=cnt, var=(0.09,) * 5, cutoff=1e-3, params=W.affine_params(A5, B5), name="affine5")
 
 
 def _tol(p):
@@ -70,6 +82,7 @@ def test_server_mix_matches_solo_and_oracle(orc):
         modes.add(info["mode"])
         _check_against_solo_and_oracle(orc, p, V, pol if p.horizon > 0 else None, info)
     assert {"stored", "otf"} <= modes
+    assert outs[[p.name for p in ps].index("uni-solo")][2]["variant"] == "fixed"
     assert st["completed"] == len(ps) and st["failed"] == 0
     assert st["hbm_in_use"] == 0 and st["active"] == 0 and st["queued"] == 0
     assert st["max_active"] > 1
@@ -98,10 +111,10 @@ def test_server_continuous_admission(orc):
 
 def test_server_errors():
     import paper_2005_06191_amd as A
-    from paper_2005_06191_amd.binding import E_NOMEM, E_UNSUPPORTED, AmyError
+    from paper_2005_06191_amd.binding import E_INVALID, E_NOMEM, AmyError
     small = W.linear2d(cells=20, precision="fp32", mode="otf", horizon=3)
     big = W.unicycle3d(nxy=100, ntheta=60, horizon=4)
-    say("[server] errors: footprint over budget, unsupported family, bad config")
+    say("[server] errors: footprint over budget, invalid problem, bad config")
     with A.Server(hbm_budget_bytes=2 << 20, max_slots=2) as srv:
         t_big = srv.submit(big)
         t_ok = srv.submit(small)
@@ -110,13 +123,10 @@ def test_server_errors():
         assert e.value.status == E_NOMEM
         V, _, _ = srv.wait(t_ok, timeout_ms=60000)
         assert V.shape == (small.n_x,)
-        # affine dynamics of dimension 5 are not compiled into the step kernel
-        lo, h, cnt = W.tiling((-1.0,) * 5, (1.0,) * 5, (3,) * 5)
-        A5 = np.eye(5) * 0.5
-        p5 = small.with_(lo=lo, h=h, count=cnt, var=(0.04,) * 5, params=W.affine_params(A5, np.zeros((5, 1))))
+        # invalid problems are refused at submission: cutoff above the peak density
         with pytest.raises(AmyError) as e:
-            srv.submit(p5)
-        assert e.value.status == E_UNSUPPORTED
+            srv.submit(small.with_(cutoff=1e3))
+        assert e.value.status == E_INVALID
         assert srv.stats()["failed"] == 1
     with pytest.raises(AmyError):
         A.Server(hbm_budget_bytes=1024, max_slots=2)

@@ -303,7 +303,7 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: device arena")
     ap.add_argument("--tune", action="store_true", help="run the autotuner before timing")
     ap.add_argument("--mode", default="otf", choices=["otf", "stored"])
-    ap.add_argument("--variant", default="auto", choices=["auto", "lanes", "fixed", "group16", "group64"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "lanes", "fixed", "group16", "group64", "factored"])
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device copy of this size 10 times (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

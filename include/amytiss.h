@@ -97,13 +97,19 @@ typedef enum { AMY_FP64 = 0, AMY_FP32 = 1 } amy_precision;
  *   GROUP16  16 lanes per state (4 states per wave) share the state's tables
  *            and split its window -- for windows of hundreds to thousands
  *            of cells;
- *   GROUP64  one wavefront per (state, input) row -- the largest windows. */
+ *   GROUP64  one wavefront per (state, input) row -- the largest windows;
+ *   FACTORED compiled shape whose innermost dimension alone moves with the
+ *            last input digit (the unicycle's heading with the turn rate):
+ *            the outer contraction is shared by all values of that digit.
+ *            Same values up to summation order (not bitwise equal to LANES).
+ * LANES, FIXED and the GROUP variants give bitwise equal results. */
 typedef enum {
   AMY_VARIANT_AUTO = 0,
   AMY_VARIANT_LANES = 1,
   AMY_VARIANT_FIXED = 2,
   AMY_VARIANT_GROUP16 = 3,
-  AMY_VARIANT_GROUP64 = 4
+  AMY_VARIANT_GROUP64 = 4,
+  AMY_VARIANT_FACTORED = 5
 } amy_variant;
 
 typedef enum {

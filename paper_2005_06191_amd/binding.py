@@ -12,7 +12,8 @@ import math
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libamytiss_hip.so")
+# AMYTISS_LIB: path of another build of the same library (e.g. for A/B timing)
+LIB_PATH = os.environ.get("AMYTISS_LIB") or os.path.join(HERE, "libamytiss_hip.so")
 
 MAX_DIM, MAX_IN, MAX_PARAMS = 8, 4, 128
 
@@ -23,7 +24,7 @@ SPEC = {"safety": 0, "reach": 1, "reach_avoid": 2}
 MODE = {"auto": 0, "stored": 1, "otf": 2}
 MODE_NAME = {v: k for k, v in MODE.items()}
 PREC = {"fp64": 0, "fp32": 1}
-VARIANT = {"auto": 0, "lanes": 1, "fixed": 2, "group16": 3, "group64": 4}
+VARIANT = {"auto": 0, "lanes": 1, "fixed": 2, "group16": 3, "group64": 4, "factored": 5}
 VARIANT_NAME = {v: k for k, v in VARIANT.items()}
 
 

@@ -27,12 +27,13 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
     if (q.mode == AMY_MODE_STORED)
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: the batched launch recomputes rows (OTF mode only)", i);
     q.mode = AMY_MODE_OTF;
-    if (q.variant == AMY_VARIANT_FIXED) q.variant = AMY_VARIANT_LANES;
+    if (q.variant == AMY_VARIANT_FIXED || q.variant == AMY_VARIANT_FACTORED) q.variant = AMY_VARIANT_LANES;
     st = amy_resolve(&q, 0, &bp.plans[i]);
     if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
     // the compiled-shape sweep is not part of the batched kernel; LANES
     // computes the same bits
-    if (bp.plans[i].dev.variant == AMY_VARIANT_FIXED) bp.plans[i].dev.variant = AMY_VARIANT_LANES;
+    if (bp.plans[i].dev.variant == AMY_VARIANT_FIXED || bp.plans[i].dev.variant == AMY_VARIANT_FACTORED)
+      bp.plans[i].dev.variant = AMY_VARIANT_LANES;
     const DevProblem& D = bp.plans[i].dev;
     if (!amy_batch_supports(D.kind, D.n, AMY_MODE_OTF))
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: dynamics kind %d with n=%d is not compiled into the batched kernel",

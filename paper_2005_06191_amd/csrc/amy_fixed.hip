@@ -236,6 +236,219 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fixed(DevProblem P, const V
   }
 }
 
+// ---------------------------------------------------------------- factored
+//
+// Inputs are walked with the last digit fastest.  When that digit moves only
+// the innermost dimension's window (dimension N-1 depends on the last digit
+// alone, and no other dimension depends on it; the unicycle: the turn rate
+// moves the heading, the speed moves x and y), every input of one
+// combination of the slower digits shares the outer dimensions' masses and
+// window.  The outer contraction is then done once per slow combination for
+// each innermost cell that the fast digit's windows can reach -- U cells
+// from the smallest of their origins -- giving A[t]; the row value of each
+// fast digit is the L_{N-1}-term sum of its innermost masses against A.
+// The host admits a problem only when the union of the fast digit's windows
+// is provably at most U cells long and dimension N-1's tables are cached.
+// Outer contraction for the U innermost cells from the union's origin:
+// acc[t] = sum over dimensions D .. N-2 of their masses times V.  Level 0 is
+// a loop (its mass read from LDS per iteration); the levels below it are
+// unrolled with their masses in registers, so every gather of one level-0
+// slice issues back to back.
+template <int D, class SH, int U, class MT, class AT, class VT>
+__device__ __forceinline__ void contract_fac_in(const FixedRow<SH, MT>& R, const VBuf<VT>& vb, uint32_t voff,
+                                                uint32_t soff, const int64_t* stride, AT (&acc)[U]) {
+#pragma unroll
+  for (int t = 0; t < U; ++t) acc[t] = AT(0);
+#pragma unroll
+  for (int k = 0; k < SH::L[D]; ++k) {
+    const uint32_t sk = soff + (uint32_t)k * (uint32_t)stride[D] * (uint32_t)sizeof(VT);
+    AT inner[U];
+    if constexpr (D == SH::N - 2) {
+#pragma unroll
+      for (int t = 0; t < U; ++t) inner[t] = AT(vb.load(voff + (uint32_t)(t * sizeof(VT)), sk));
+    } else {
+      contract_fac_in<D + 1, SH, U, MT, AT, VT>(R, vb, voff, sk, stride, inner);
+    }
+#pragma unroll
+    for (int t = 0; t < U; ++t) acc[t] = fma_(AT(R.m[D][k]), inner[t], acc[t]);
+  }
+}
+
+template <class SH, int U, class MT, class AT, class VT, bool COMP>
+__device__ __forceinline__ void contract_fac(const DevProblem& P, const FixedRow<SH, MT>& R, const MT* m0,
+                                             const VBuf<VT>& vb, uint32_t voff, AT (&acc)[U]) {
+  AT c[U];
+#pragma unroll
+  for (int t = 0; t < U; ++t) acc[t] = c[t] = AT(0);
+#pragma clang loop unroll(disable)
+  for (int k = 0; k < SH::L[0]; ++k) {
+    const uint32_t soff = (uint32_t)k * (uint32_t)P.stride[0] * (uint32_t)sizeof(VT);
+    AT inner[U];
+    if constexpr (SH::N == 2) {
+#pragma unroll
+      for (int t = 0; t < U; ++t) inner[t] = AT(vb.load(voff + (uint32_t)(t * sizeof(VT)), soff));
+    } else {
+      contract_fac_in<1, SH, U, MT, AT, VT>(R, vb, voff, soff, P.stride, inner);
+    }
+    const AT mk = AT(m0[k * FIX_BLOCK]);
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      if constexpr (COMP) {
+        const AT y = mk * inner[t] - c[t];
+        const AT s2 = acc[t] + y;
+        c[t] = (s2 - acc[t]) - y;
+        acc[t] = s2;
+      } else {
+        acc[t] = fma_(mk, inner[t], acc[t]);
+      }
+    }
+  }
+}
+
+// Masses and window origins of the outer dimensions 0 .. N-2 for the
+// current combination of the slow digits: cached tables are read from LDS;
+// the others are built from the mean mu.  Dimension 0's masses are left in
+// LDS (m0: its cached table, or the lane's slot t0 when it is built here),
+// the others go to registers.
+template <int I, class SH, class MT, bool TAIL>
+__device__ __forceinline__ void fac_outer(const DevProblem& P, const InputWalk& iw, const LaneLds<MT>& S,
+                                          MT* t0, const double* mu, FixedRow<SH, MT>& R, const MT*& m0,
+                                          uint32_t& base, double& win, double& grid) {
+  if constexpr (I < SH::N - 1) {
+    constexpr int L = SH::L[I];
+    int o;
+    if (P.ccount[I] > 0) {
+      const int c = combo_index(P, I, iw);
+      const MT* tp = S.tab + (P.toff[I] + c * L) * FIX_BLOCK;
+      if constexpr (I == 0) {
+        m0 = tp;
+      } else {
+#pragma unroll
+        for (int k = 0; k < L; ++k) R.m[I][k] = tp[k * FIX_BLOCK];
+      }
+      o = S.org[(P.ooff[I] + c) * FIX_BLOCK];
+      if constexpr (TAIL) {
+        win *= S.wg[(2 * (P.ooff[I] + c)) * FIX_BLOCK];
+        grid *= S.wg[(2 * (P.ooff[I] + c) + 1) * FIX_BLOCK];
+      }
+    } else {
+      const Win w = window_1d(P, I, mu[I]);
+      fixed_table<MT, L>(P, I, w, R.m[I]);
+      if constexpr (I == 0) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) t0[k * FIX_BLOCK] = R.m[0][k];
+        m0 = t0;
+      }
+      o = w.o;
+      if constexpr (TAIL) {
+        double wm, gm;
+        win_grid_mass(P, I, w, wm, gm);
+        win *= wm;
+        grid *= gm;
+      }
+    }
+    base += (uint32_t)o * (uint32_t)P.stride[I];
+    fac_outer<I + 1, SH, MT, TAIL>(P, iw, S, t0, mu, R, m0, base, win, grid);
+  }
+}
+
+template <int KIND, class SH, int U, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+__global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fac(DevProblem P, const VI* __restrict__ Vin,
+                                                         VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                                         int16_t* __restrict__ pol,
+                                                         unsigned long long* __restrict__ tailmax,
+                                                         uint32_t t0_off) {
+  constexpr int N = SH::N;
+  constexpr int F = N - 1;
+  constexpr int LF = SH::L[F];
+  static_assert(N >= 2 && LF <= U, "factored sweep shape");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const LaneLds<MT> S(P, smem, threadIdx.x);
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * FIX_BLOCK + threadIdx.x;
+  double tmax = 0.0;
+  if (s < (uint32_t)P.n_x) {
+    const uint8_t lb = label[s];
+    if (lb != LBL_FREE) {
+      Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
+      if (pol) pol[s] = -1;
+    } else {
+      double x[N];
+      state_centre<N>(P, s, x);
+      typename Dyn<KIND, N>::State st;
+      Dyn<KIND, N>::prep(P, x, st);
+      build_cached<KIND, N, MT, TAIL, FIX_BLOCK>(P, st, x, S);
+      const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
+      const int fd = P.m - 1;                    // the fast digit
+      const int nf = P.ucount[fd];
+      const int fm = P.dep_mult[F][fd];          // its step in dimension F's combo index
+      // smallest innermost origin over the fast digit
+      int omin = S.org[P.ooff[F] * FIX_BLOCK];
+      for (int f = 1; f < nf; ++f) omin = min(omin, S.org[(P.ooff[F] + f * fm) * FIX_BLOCK]);
+      FixedRow<SH, MT> R;
+      MT* t0 = reinterpret_cast<MT*>(smem + t0_off) + threadIdx.x;
+      bool all_cached = true;
+#pragma unroll
+      for (int i = 0; i < F; ++i) all_cached = all_cached && P.ccount[i] > 0;
+      InputWalk iw;
+      iw.reset();
+      AT best = AT(-1);
+      int arg = 0, u = 0;
+      const int nslow = P.n_u / nf;
+      for (int sc = 0; sc < nslow; ++sc) {
+        uint32_t base = (uint32_t)omin;
+        double win = 1.0, grid = 1.0;
+        double mu[N];
+        if (!all_cached) {  // the slow digits' mean (the fast digit is 0 here)
+          double uv[AMY_MAXI];
+          iw.values(P, uv);
+          Dyn<KIND, N>::apply(P, st, x, uv, mu);
+        }
+        const MT* m0 = nullptr;
+        fac_outer<0, SH, MT, TAIL>(P, iw, S, t0, mu, R, m0, base, win, grid);
+        AT A[U];
+        contract_fac<SH, U, MT, AT, VI, COMP>(P, R, m0, vb, base * (uint32_t)sizeof(VI), A);
+        for (int f = 0; f < nf; ++f, ++u) {
+          const int c = f * fm;
+          const MT* tp = S.tab + (P.toff[F] + c * LF) * FIX_BLOCK;
+          const int d = min(S.org[(P.ooff[F] + c) * FIX_BLOCK] - omin, U - LF);
+          AT q = AT(0);
+#pragma unroll
+          for (int k = 0; k < LF; ++k) {
+            AT a = A[k];
+#pragma unroll
+            for (int j = 1; j <= U - LF; ++j) a = (d == j) ? A[j + k] : a;
+            q = fma_(AT(tp[k * FIX_BLOCK]), a, q);
+          }
+          if constexpr (TAIL) {
+            const double wf = S.wg[(2 * (P.ooff[F] + c)) * FIX_BLOCK];
+            const double gf = S.wg[(2 * (P.ooff[F] + c) + 1) * FIX_BLOCK];
+            tmax = fmax(tmax, grid * gf - win * wf);
+          }
+          if (q > best) {
+            best = q;
+            arg = u;
+          }
+        }
+        // next combination of the slow digits (the fast digit stays 0)
+#pragma unroll
+        for (int k = AMY_MAXI - 1; k >= 0; --k) {
+          if (k < fd) {
+            if (++iw.dig[k] < P.ucount[k]) break;
+            iw.dig[k] = 0;
+          }
+        }
+      }
+      Vout[s] = VO(best);
+      if (pol) pol[s] = (int16_t)arg;
+    }
+  }
+  if constexpr (TAIL) {
+    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+    if ((threadIdx.x & 63) == 0 && tmax > 0.0)
+      atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+  }
+}
+
 // ------------------------------------------------------------- launchers
 
 template <int KIND, class SH>
@@ -268,6 +481,51 @@ struct FixedLaunch {
   }
 };
 
+// Factored launch of a shape (U: innermost cells reachable by the fast digit).
+template <int KIND, class SH, int U>
+struct FacLaunch {
+  // dimension N-1 depends on the last input digit alone and its tables are
+  // cached, no other dimension depends on that digit, and the fast digit's
+  // windows span at most U innermost cells
+  static bool feasible(const DevProblem& P) {
+    if (!FixedLaunch<KIND, SH>::matches(P) || P.nocut) return false;
+    const int F = SH::N - 1, fd = P.m - 1;
+    if (P.dep_mult[F][fd] <= 0) return false;
+    for (int k = 0; k < fd; ++k)
+      if (P.dep_mult[F][k] != 0) return false;
+    for (int i = 0; i < F; ++i)
+      if (P.dep_mult[i][fd] != 0) return false;
+    if (P.ccount[F] <= 0) return false;
+    return span_bound(P) <= U;
+  }
+  // Window origins move by at most ceil(drift range / h) cells over the fast
+  // digit, plus one for rounding at a cell boundary; the union adds L_F.
+  static int span_bound(const DevProblem& P);
+  template <class MT, class AT, class VI, class VO, bool COMP>
+  static void go(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                 unsigned long long* tailmax, hipStream_t st) {
+    const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
+    // the block's tables, then one slot of dimension 0's masses per lane
+    const uint32_t t0 = (uint32_t)(((tailmax ? P.lds_bytes_tail : P.lds_bytes_fixed) + 15) & ~15);
+    const size_t lds = t0 + (size_t)SH::L[0] * sizeof(MT) * FIX_BLOCK;
+    if (tailmax)
+      hipLaunchKernelGGL((k_sweep_fac<KIND, SH, U, MT, AT, VI, VO, COMP, true>), g, b, lds, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax, t0);
+    else
+      hipLaunchKernelGGL((k_sweep_fac<KIND, SH, U, MT, AT, VI, VO, COMP, false>), g, b, lds, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax, t0);
+  }
+  static hipError_t sweep(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout, const uint8_t* label,
+                          int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
+    switch (sk) {
+      case SWEEP_F64: go<double, double, double, double, false>(P, Vin, Vout, label, pol, tailmax, st); break;
+      case SWEEP_F32: go<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, st); break;
+      case SWEEP_F32_LAST: go<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, st); break;
+    }
+    return hipGetLastError();
+  }
+};
+
 // Window shapes of the workload families (2-D linear, 3-D unicycle, 5-D
 // room ring, 7-D vehicle).
 // (first argument: the most gathers issued as one unrolled block)
@@ -280,6 +538,35 @@ using ShapeLinear2 = ShapeT<28, 28, 28>;
   X(AMY_DYN_ROOM_, ShapeRoom5)         \
   X(AMY_DYN_VEHICLE7_, ShapeVehicle7)  \
   X(AMY_DYN_AFFINE_, ShapeLinear2)
+
+// Unicycle: the heading moves by tau * omega, omega the last input.
+template <>
+int FacLaunch<AMY_DYN_UNICYCLE_, ShapeUnicycle, 5>::span_bound(const DevProblem& P) {
+  const int F = 2, fd = P.m - 1;
+  const double range = fabs(P.params[0]) * (P.uhi[fd] - P.ulo[fd]);
+  return (int)ceil(range * P.inv_h[F] - 1e-12) + 1 + P.L[F];
+}
+
+#define AMY_FAC_SHAPES(X) X(AMY_DYN_UNICYCLE_, ShapeUnicycle, 5)
+
+bool amy_fac_available(const DevProblem& P) {
+  const uint64_t vbytes = (uint64_t)P.n_x * 8u;
+  if (vbytes >= (1ull << 32)) return false;
+#define X(K, SH, U) \
+  if (FacLaunch<K, SH, U>::feasible(P)) return true;
+  AMY_FAC_SHAPES(X)
+#undef X
+  return false;
+}
+
+hipError_t amy_launch_sweep_fac(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
+#define X(K, SH, U) \
+  if (FacLaunch<K, SH, U>::feasible(P)) return FacLaunch<K, SH, U>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+  AMY_FAC_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
 
 bool amy_fixed_available(const DevProblem& P) {
   // buffer byte offsets are 32-bit

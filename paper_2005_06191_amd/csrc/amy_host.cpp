@@ -93,7 +93,7 @@ amy_status amy_validate(const amy_problem* p) {
   if (p->spec < AMY_SAFETY || p->spec > AMY_REACH_AVOID) return amy_fail(AMY_E_INVALID, "bad spec");
   if (p->mode < AMY_MODE_AUTO || p->mode > AMY_MODE_OTF) return amy_fail(AMY_E_INVALID, "bad mode");
   if (p->precision != AMY_FP64 && p->precision != AMY_FP32) return amy_fail(AMY_E_INVALID, "bad precision");
-  if (p->variant < AMY_VARIANT_AUTO || p->variant > AMY_VARIANT_GROUP64) return amy_fail(AMY_E_INVALID, "bad variant");
+  if (p->variant < AMY_VARIANT_AUTO || p->variant > AMY_VARIANT_FACTORED) return amy_fail(AMY_E_INVALID, "bad variant");
   const int ep = expected_params(p);
   if (ep < 0) return amy_fail(AMY_E_INVALID, "bad dynamics kind %d", p->dyn.kind);
   if (p->dyn.kind == AMY_DYN_UNICYCLE && (n != 3 || m != 2))
@@ -359,6 +359,7 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   // LDS; the group variants need one set per state of the block
   const bool lanes_ok = (plan_tables(p, pl) == AMY_OK);
   const bool fixed_ok = lanes_ok && amy_fixed_available(pl->dev);
+  const bool fac_ok = fixed_ok && mode == AMY_MODE_OTF && amy_fac_available(pl->dev);
   int64_t sum_l = 0;
   for (int i = 0; i < pl->dev.n; ++i) sum_l += pl->dev.L[i];
   const int64_t msz = pl->f64 ? 8 : 4;
@@ -368,6 +369,7 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
     switch (v) {
       case AMY_VARIANT_LANES: return lanes_ok;
       case AMY_VARIANT_FIXED: return fixed_ok;
+      case AMY_VARIANT_FACTORED: return fac_ok;
       case AMY_VARIANT_GROUP16: return g16_ok && mode == AMY_MODE_OTF;
       case AMY_VARIANT_GROUP64: return g64_ok && mode == AMY_MODE_OTF;
     }
@@ -386,7 +388,8 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
     // one lane per state while its tables leave room for >= 6 waves per CU
     // and the window is small; otherwise lanes share a state's window
     const bool lanes_light = lanes_ok && pl->dev.lds_bytes_tail <= 24 * 1024 && pl->W < 1024;
-    if (fixed_ok) v = AMY_VARIANT_FIXED;
+    if (fac_ok) v = AMY_VARIANT_FACTORED;
+    else if (fixed_ok) v = AMY_VARIANT_FIXED;
     else if (lanes_light) v = AMY_VARIANT_LANES;
     else if (pl->W >= 4096 && g64_ok) v = AMY_VARIANT_GROUP64;
     else if (g16_ok) v = AMY_VARIANT_GROUP16;
@@ -411,7 +414,8 @@ static void fill_info(const amy_problem* p, const Plan& pl, amy_info* info) {
   for (int i = 0; i < p->grid.n; ++i)
     if (pl.dev.ccount[i] > 0) info->table_cache_mask |= 1 << i;
   info->lds_bytes = (pl.dev.grp_g > 1) ? pl.dev.lds_bytes_group
-                    : (pl.dev.variant == AMY_VARIANT_FIXED ? pl.dev.lds_bytes_fixed : pl.dev.lds_bytes);
+                    : ((pl.dev.variant == AMY_VARIANT_FIXED || pl.dev.variant == AMY_VARIANT_FACTORED)
+                           ? pl.dev.lds_bytes_fixed : pl.dev.lds_bytes);
   info->n_x = pl.dev.n_x;
   info->n_u = pl.dev.n_u;
   info->rows = pl.rows;
@@ -450,6 +454,7 @@ hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_
   if (pl.mode == AMY_MODE_STORED)
     return amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
                                    label, pk, st);
+  if (D.variant == AMY_VARIANT_FACTORED) return amy_launch_sweep_fac(D, sk, Vb[cur], out, label, pk, tail, st);
   if (D.variant == AMY_VARIANT_FIXED) return amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk, tail, st);
   if (D.grp_g > 1) return amy_launch_sweep_group(D, sk, Vb[cur], out, label, pk, tail, st);
   return amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk, tail, st);

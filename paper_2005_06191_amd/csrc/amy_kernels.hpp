@@ -37,3 +37,7 @@ bool amy_fixed_available(const DevProblem& P);
 hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
                                   const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
                                   hipStream_t st);
+// Factored compiled-shape sweep (inputs sharing the outer dimensions' windows).
+bool amy_fac_available(const DevProblem& P);
+hipError_t amy_launch_sweep_fac(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
+                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax, hipStream_t st);

@@ -451,7 +451,8 @@ extern "C" amy_status amy_server_submit(amy_server* s, const amy_problem* p, int
   // launch per step; the rest share the batched step, which runs the
   // run-time-window code (same bits as the compiled-shape sweep)
   r->solo = r->plan.dev.n_x >= SOLO_STATES || !amy_batch_supports(r->plan.dev.kind, r->plan.dev.n, r->plan.mode);
-  if (!r->solo && r->plan.dev.variant == AMY_VARIANT_FIXED) r->plan.dev.variant = AMY_VARIANT_LANES;
+  if (!r->solo && (r->plan.dev.variant == AMY_VARIANT_FIXED || r->plan.dev.variant == AMY_VARIANT_FACTORED))
+    r->plan.dev.variant = AMY_VARIANT_LANES;
   r->off_v = al256(r->plan.ws_bytes);
   r->off_pol = al256(r->off_v + (uint64_t)r->plan.dev.n_x * 8);
   r->bytes = r->off_pol + (r->want_policy ? al256((uint64_t)p->horizon * r->plan.dev.n_x * 2) : 0);

@@ -105,7 +105,8 @@ extern "C" amy_status amy_tune_solve(const amy_problem* p, void* stream, void* w
   amy_status st = amy_validate(p);
   if (st != AMY_OK) return st;
   std::vector<int> variants;
-  for (int v : {AMY_VARIANT_LANES, AMY_VARIANT_FIXED, AMY_VARIANT_GROUP16, AMY_VARIANT_GROUP64}) {
+  for (int v : {AMY_VARIANT_LANES, AMY_VARIANT_FIXED, AMY_VARIANT_GROUP16, AMY_VARIANT_GROUP64,
+                AMY_VARIANT_FACTORED}) {
     amy_problem q = *p;
     q.variant = v;
     Plan pl;
@@ -245,7 +246,7 @@ extern "C" amy_status amy_tune_load(const char* path) {
     if (sscanf(body.c_str(), "{\"chunk\": %d, \"blocks_per_cu\": %d, \"xcd_order\": %d, \"variant\": %d, \"ms\": %lf}",
                &e.chunk, &e.blocks_per_cu, &e.xcd_order, &e.variant, &e.ms) != 5)
       return amy_fail(AMY_E_INVALID, "%s: malformed entry for %s", path, key.c_str());
-    if (e.chunk < 1 || e.chunk > 64 || e.blocks_per_cu < 0 || e.variant < 0 || e.variant > AMY_VARIANT_GROUP64)
+    if (e.chunk < 1 || e.chunk > 64 || e.blocks_per_cu < 0 || e.variant < 0 || e.variant > AMY_VARIANT_FACTORED)
       return amy_fail(AMY_E_INVALID, "%s: out-of-range entry for %s", path, key.c_str());
     loaded[key] = e;
     pos = b1 + 1;

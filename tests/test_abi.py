@@ -94,3 +94,21 @@ def test_too_many_states_unsupported(A):
     with pytest.raises(A.AmyError) as e:
         A.query(p)
     assert e.value.status == A.binding.E_UNSUPPORTED
+
+
+def test_variant_choice_on_the_host(A):
+    """Variant feasibility is decided on the host: the factored sweep only
+    where the last input digit moves the innermost window alone within the
+    compiled bound (the unicycle workload), the compiled shapes only for
+    their windows; AUTO picks the factored sweep where it applies."""
+    uni = W.unicycle3d()
+    assert A.query(uni)["variant"] == "factored"
+    assert A.query(uni, variant="fixed")["variant"] == "fixed"
+    assert A.query(uni, variant="lanes")["variant"] == "lanes"
+    # a faster turn rate widens the heading windows' union beyond the bound
+    fast = uni.with_(u_lo=(0.0, -3.0), u_hi=(1.0, 3.0))
+    assert A.query(fast)["variant"] != "factored"
+    for p in (W.room5d(), W.linear2d(mode="otf"), W.vehicle7d(), uni.with_(mode="stored")):
+        with pytest.raises(A.AmyError) as e:
+            A.query(p, variant="factored")
+        assert e.value.status == A.binding.E_UNSUPPORTED

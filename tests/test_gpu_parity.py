@@ -194,7 +194,7 @@ def test_fixed_shape_kernel_matches_generic(name):
     the same order: results are bitwise equal."""
     import paper_2005_06191_amd as A
     p = CASES[name]().with_(horizon=4)
-    assert A.query(p)["variant"] == "fixed"
+    assert A.query(p)["variant"] in ("fixed", "factored")
     say(f"[fixed vs lanes] {name}")
     a = A.solve(p, variant="fixed")
     b = A.solve(p, variant="lanes")
@@ -202,6 +202,40 @@ def test_fixed_shape_kernel_matches_generic(name):
     assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())
     assert np.array_equal(a.policy.cpu().numpy(), b.policy.cpu().numpy())
     assert a.info["max_row_tail"] == b.info["max_row_tail"]
+
+
+@pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "unicycle-patch-reach-fp32"])
+def test_factored_sweep_matches_oracle_and_fixed(orc, name):
+    """The factored sweep shares the outer contraction between inputs that
+    differ only in the last digit: the window sum is re-associated, so it is
+    checked against the oracle at the precision's tolerance and against the
+    compiled-shape sweep at the same tolerance; the FP64 tail is the same."""
+    import paper_2005_06191_amd as A
+    p = CASES[name]()
+    tol = TOL_FP64 if p.precision == "fp64" else TOL_FP32
+    say(f"[factored] {name}")
+    a = A.solve(p, variant="factored")
+    assert a.info["variant"] == "factored"
+    V, pol = a.V.cpu().numpy(), a.policy.cpu().numpy()
+    ref = orc.solve(p, gap=True)
+    compare(p, ref, V, pol, tol, gap=ref["gap"])
+    b = A.solve(p, variant="fixed")
+    assert float(np.abs(V - b.V.cpu().numpy()).max()) <= tol
+    assert a.info["max_row_tail"] == b.info["max_row_tail"]
+
+
+def test_factored_full_size_vs_fixed():
+    import paper_2005_06191_amd as A
+    p = W.unicycle3d().with_(horizon=6)
+    say("[factored] unicycle 100x100x60, T_d = 6, vs fixed")
+    a = A.solve(p, variant="factored", policy=False)
+    b = A.solve(p, variant="fixed", policy=False)
+    assert a.info["variant"] == "factored"
+    assert float(np.abs(a.V.cpu().numpy() - b.V.cpu().numpy()).max()) <= TOL_FP32
+    q = p.with_(precision="fp64")
+    a = A.solve(q, variant="factored", policy=False)
+    b = A.solve(q, variant="fixed", policy=False)
+    assert float(np.abs(a.V.cpu().numpy() - b.V.cpu().numpy()).max()) <= TOL_FP64
 
 
 def test_vehicle7_full_fixed_vs_generic_first_step():

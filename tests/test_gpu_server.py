@@ -82,7 +82,7 @@ def test_server_mix_matches_solo_and_oracle(orc):
         modes.add(info["mode"])
         _check_against_solo_and_oracle(orc, p, V, pol if p.horizon > 0 else None, info)
     assert {"stored", "otf"} <= modes
-    assert outs[[p.name for p in ps].index("uni-solo")][2]["variant"] == "fixed"
+    assert outs[[p.name for p in ps].index("uni-solo")][2]["variant"] in ("fixed", "factored")
     assert st["completed"] == len(ps) and st["failed"] == 0
     assert st["hbm_in_use"] == 0 and st["active"] == 0 and st["queued"] == 0
     assert st["max_active"] > 1

@@ -181,8 +181,9 @@ typedef struct {
   double tail_bound_E;           /* T_d * max_row_tail: V_{no cut} <= V + E  */
   /* phase times (HIP events on the solve's stream), filled when info != NULL:
    * build = labels, tail and (STORED) row construction; sweeps = all T_d
-   * Bellman steps; main_sweeps = the first T_d - 1 of them (the steps that
-   * read and write the working precision; the last step writes FP64 V). */
+   * Bellman steps; main_sweeps = steps k = T_d - 1 .. 2, the T_d - 2 launches
+   * of the working-precision sweep alone (the first step also computes the
+   * FP64 tail, the last one writes FP64 V; 0 when T_d < 3). */
   double t_build_ms, t_sweeps_ms, t_main_sweeps_ms, t_readout_ms, t_total_ms;
 } amy_info;
 

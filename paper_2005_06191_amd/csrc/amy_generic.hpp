@@ -220,6 +220,12 @@ __device__ __forceinline__ void write_row(const DevProblem& P, const MT* __restr
 }
 
 // Alg. 2: every row of T once, plus (TAIL) the FP64 max row tail.
+// Flat V offsets of the W window slots (row-major, last dimension fastest),
+// stored after the rows' origins: the same for every row.
+__device__ __forceinline__ const int32_t* slot_offsets(const DevProblem& P, const int32_t* org) {
+  return org + (int64_t)((P.n_x + LANE_BLOCK - 1) / LANE_BLOCK) * LANE_BLOCK * P.n_u;
+}
+
 template <int KIND, int N, class MT, bool TAIL>
 __global__ void __launch_bounds__(LANE_BLOCK) k_build(DevProblem P, const uint8_t* __restrict__ label,
                                                       MT* __restrict__ T, int32_t* __restrict__ org,
@@ -227,6 +233,18 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_build(DevProblem P, const uint8_
   extern __shared__ __align__(16) unsigned char smem[];
   const LaneLds<MT> S(P, smem, threadIdx.x);
   const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
+  if (blockIdx.x == 0) {
+    int32_t* offs = const_cast<int32_t*>(slot_offsets(P, org));
+    for (int k = threadIdx.x; k < P.W; k += LANE_BLOCK) {
+      int r = k;
+      int64_t off = 0;
+      for (int i = N - 1; i >= 0; --i) {
+        off += (int64_t)(r % P.L[i]) * P.stride[i];
+        r /= P.L[i];
+      }
+      offs[k] = (int32_t)off;
+    }
+  }
   double tmax = 0.0;
   if (s < (uint32_t)P.n_x && label[s] == LBL_FREE) {
     double x[N];
@@ -257,25 +275,44 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_build(DevProblem P, const uint8_
   if constexpr (TAIL) wave_max_to(tmax, tailmax);
 }
 
-template <int D, int N, class MT, class AT, class VT, bool COMP>
-__device__ __forceinline__ void stored_sum(const DevProblem& P, const MT* __restrict__& t,
-                                           const VT* __restrict__ V, int64_t base, AT& acc, AT& c) {
-  for (int k = 0; k < P.L[D]; ++k) {
-    if constexpr (D == N - 1) {
-      const AT term = AT(*t) * AT(V[base + k]);
-      t += LANE_BLOCK;
-      if constexpr (COMP) {
-        const AT y = term - c;
-        const AT s2 = acc + y;
-        c = (s2 - acc) - y;
-        acc = s2;
-      } else {
-        acc = acc + term;
-      }
+// One stored row: sum over the W slots, in slot order, of T * V.  The slot
+// offsets are uniform (scalar loads); V is gathered through a buffer view
+// at the row's origin, T is streamed with non-temporal loads.  Eight slots'
+// loads are issued before their products are summed.
+template <class MT, class AT, class VT, bool COMP>
+__device__ __forceinline__ AT stored_row(int W, const MT* __restrict__ t, __amdgpu_buffer_rsrc_t vr,
+                                         uint32_t voff, const int32_t* __restrict__ offs) {
+  AT acc = AT(0), c = AT(0);
+  auto add = [&](AT term) {
+    if constexpr (COMP) {
+      const AT y = term - c;
+      const AT s2 = acc + y;
+      c = (s2 - acc) - y;
+      acc = s2;
     } else {
-      stored_sum<D + 1, N, MT, AT, VT, COMP>(P, t, V, base + (int64_t)k * P.stride[D], acc, c);
+      acc = acc + term;
     }
+  };
+  auto vload = [&](int32_t o) -> VT {
+    if constexpr (sizeof(VT) == 8)
+      return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b64(vr, (int)voff, o * 8, 0));
+    else
+      return __builtin_bit_cast(VT, __builtin_amdgcn_raw_buffer_load_b32(vr, (int)voff, o * 4, 0));
+  };
+  int k = 0;
+  for (; k + 8 <= W; k += 8) {
+    MT tv[8];
+    VT vv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      tv[j] = __builtin_nontemporal_load(t + (int64_t)(k + j) * LANE_BLOCK);
+      vv[j] = vload(offs[k + j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) add(AT(tv[j]) * AT(vv[j]));
   }
+  for (; k < W; ++k) add(AT(__builtin_nontemporal_load(t + (int64_t)k * LANE_BLOCK)) * AT(vload(offs[k])));
+  return acc;
 }
 
 template <int N, class MT, class AT, class VI, class VO, bool COMP>
@@ -291,14 +328,16 @@ __device__ __forceinline__ void stored_tile(const DevProblem& P, uint32_t s, con
     return;
   }
   const int64_t tile = s / LANE_BLOCK, lane = s % LANE_BLOCK;
+  const int32_t* offs = slot_offsets(P, org);
+  const __amdgpu_buffer_rsrc_t vr =
+      __builtin_amdgcn_make_buffer_rsrc((void*)Vin, (short)0, (int)((uint32_t)P.n_x * (uint32_t)sizeof(VI)), 0x00020000);
   AT best = AT(-1);
   int arg = 0;
   for (int u = 0; u < P.n_u; ++u) {
     const int64_t rt = tile * P.n_u + u;
     const MT* t = T + rt * (int64_t)P.W * LANE_BLOCK + lane;
-    const int64_t base = org[rt * LANE_BLOCK + lane];
-    AT acc = AT(0), c = AT(0);
-    stored_sum<0, N, MT, AT, VI, COMP>(P, t, Vin, base, acc, c);
+    const uint32_t voff = (uint32_t)org[rt * LANE_BLOCK + lane] * (uint32_t)sizeof(VI);
+    const AT acc = stored_row<MT, AT, VI, COMP>(P.W, t, vr, voff, offs);
     if (acc > best) {
       best = acc;
       arg = u;

@@ -299,7 +299,7 @@ void amy_make_plan(const amy_problem* p, Plan* pl) {
 
 static inline uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-// Workspace: labels | V0 | V1 | tail max | (stored: T rows | origins).
+// Workspace: labels | V0 | V1 | tail max | (stored: T rows | origins | slot offsets).
 // T is kept in the precision of the path (FP32 rows for the FP32 path,
 // as the paper's own memory figures imply; FP64 rows for the plain path).
 void amy_layout(Plan* pl, int mode) {
@@ -316,7 +316,7 @@ void amy_layout(Plan* pl, int mode) {
     const uint64_t tiles = (nx + 63) / 64;
     const uint64_t rows_p = tiles * 64 * (uint64_t)D.n_u;
     pl->off_T = o;    o = align256(o + rows_p * (uint64_t)pl->W * vs);
-    pl->off_org = o;  o = align256(o + rows_p * 4);
+    pl->off_org = o;  o = align256(o + rows_p * 4 + (uint64_t)pl->W * 4);  // + slot offsets
     pl->stored_bytes = o - pl->off_T;
   }
   pl->mode = mode;
@@ -486,9 +486,13 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
     if (tm && k == 1) hipEventRecord(tm->ev[2], st);
     if ((e = amy_enqueue_step(pl, st, ws, V_out, pol, horizon, k, want_tail)) != hipSuccess)
       return amy_hip_fail(e, "sweep kernel");
+    if (tm && k == horizon) hipEventRecord(tm->ev[5], st);
   }
   if (tm) {
-    if (horizon == 0) hipEventRecord(tm->ev[2], st);
+    if (horizon == 0) {
+      hipEventRecord(tm->ev[5], st);
+      hipEventRecord(tm->ev[2], st);
+    }
     hipEventRecord(tm->ev[3], st);
     hipEventRecord(tm->ev[4], st);
   }
@@ -532,7 +536,8 @@ extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* worksp
       info->t_build_ms = ms;
       hipEventElapsedTime(&ms, tm.ev[1], tm.ev[3]);
       info->t_sweeps_ms = ms;
-      hipEventElapsedTime(&ms, tm.ev[1], tm.ev[2]);
+      ms = 0.f;
+      if (p->horizon >= 3) hipEventElapsedTime(&ms, tm.ev[5], tm.ev[2]);
       info->t_main_sweeps_ms = ms;
       hipEventElapsedTime(&ms, tm.ev[3], tm.ev[4]);
       info->t_readout_ms = ms;

@@ -16,10 +16,10 @@ struct Plan {
   uint64_t stored_bytes, ws_bytes;
 };
 
-// ev[0] start, ev[1] sweeps begin, ev[2] after the first T_d - 1 sweeps,
-// ev[3] after the last sweep, ev[4] end.
+// ev[0] start, ev[1] sweeps begin, ev[5] after the first sweep (k = T_d),
+// ev[2] after the first T_d - 1 sweeps, ev[3] after the last sweep, ev[4] end.
 struct Timing {
-  static const int N = 5;
+  static const int N = 6;
   hipEvent_t ev[N];
 };
 

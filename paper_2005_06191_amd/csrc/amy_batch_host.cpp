@@ -32,8 +32,10 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
     if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
     // the compiled-shape sweep is not part of the batched kernel; LANES
     // computes the same bits
-    if (bp.plans[i].dev.variant == AMY_VARIANT_FIXED || bp.plans[i].dev.variant == AMY_VARIANT_FACTORED)
+    if (bp.plans[i].dev.variant == AMY_VARIANT_FIXED || bp.plans[i].dev.variant == AMY_VARIANT_FACTORED) {
       bp.plans[i].dev.variant = AMY_VARIANT_LANES;
+      bp.plans[i].dev.rel_entries = 0;
+    }
     const DevProblem& D = bp.plans[i].dev;
     if (!amy_batch_supports(D.kind, D.n, AMY_MODE_OTF))
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: dynamics kind %d with n=%d is not compiled into the batched kernel",

@@ -449,6 +449,219 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fac(DevProblem P, const VI*
   }
 }
 
+// --------------------------------------------------- shared relative tables
+//
+// For the unicycle the mean minus the state's own cell centre is
+// (tau v cos th, tau v sin th, tau omega): in x and y it depends only on the
+// heading cell and the speed, in the heading only on the turn rate.  The
+// 1-D masses of a window relative to the state's cell are then the same for
+// every state with that heading cell, so they are built once per solve
+// (k_rel_build) and read by the steps without the FP64 tail (k_sweep_rel).
+// A state's window origin is its cell plus the relative origin, clamped to
+// the grid as the per-state rule clamps it; slots are matched to the
+// relative masses by the clamp's shift, and cells outside the grid or the
+// kept range get mass 0 -- the same cells and masses as the per-state rule.
+template <int KIND, int N>
+struct RelDrift {
+  static constexpr bool ok = false;
+};
+
+template <>
+struct RelDrift<AMY_DYN_UNICYCLE_, 3> {
+  static constexpr bool ok = true;
+  static constexpr int ctx(int i) { return i < 2 ? 2 : -1; }
+  // mean of dimension i minus the state's cell centre; xc: the centre of
+  // the context dimension's cell
+  __device__ static double drift(const DevProblem& P, int i, double xc, const double* u) {
+    const double tau = P.params[0];
+    if (i == 2) return tau * u[1];
+    const double a = tau * u[0];
+    return i == 0 ? a * cos(xc) : a * sin(xc);
+  }
+};
+
+#define REL_SLOTS 8  // relative table entry: up to 8 masses
+
+template <int KIND, int N, class MT>
+__global__ void __launch_bounds__(64) k_rel_build(DevProblem P, MT* __restrict__ rm, int32_t* __restrict__ rlo) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  if (e >= P.rel_entries) return;
+  int i = 0;
+#pragma unroll
+  for (int d = 1; d < N; ++d)
+    if (e >= P.rel_off[d]) i = d;
+  const int jc = e - P.rel_off[i];
+  const int j = jc / P.rcount[i], c = jc % P.rcount[i];
+  InputWalk iw;
+#pragma unroll
+  for (int k = 0; k < AMY_MAXI; ++k) {
+    const int mlt = P.rmult[i][k];
+    iw.dig[k] = (k < P.m && mlt > 0) ? (c / mlt) % P.ucount[k] : 0;
+  }
+  double u[AMY_MAXI];
+  iw.values(P, u);
+  const int cx = P.rctx[i];
+  const double xc = cx >= 0 ? P.lo[cx] + ((double)j + 0.5) * P.h[cx] : 0.0;
+  const double dr = RelDrift<KIND, N>::drift(P, i, xc, u);
+  // kept cells r (relative to the state's cell): |r h - drift| <= x*
+  const int L = P.L[i];
+  const int r0 = (int)ceil((dr - P.xstar[i]) * P.inv_h[i]);
+  int r1 = (int)floor((dr + P.xstar[i]) * P.inv_h[i]);
+  r1 = min(r1, r0 + L - 1);
+  const int cnt = max(0, r1 - r0 + 1);
+  // edge below relative cell r: z = ((r - 1/2) h - drift) / sigma
+  double zp = (((double)r0 - 0.5) * P.h[i] - dr) * P.inv_sigma[i];
+  MT ep = ec_of(zp, MT());
+  for (int k = 0; k < REL_SLOTS; ++k) {
+    MT mk = MT(0);
+    if (k < cnt) {
+      const double z = (((double)(r0 + k) + 0.5) * P.h[i] - dr) * P.inv_sigma[i];
+      const MT ez = ec_of(z, MT());
+      mk = mass_of(zp, ep, z, ez);
+      zp = z;
+      ep = ez;
+    }
+    rm[(int64_t)e * REL_SLOTS + k] = mk;
+  }
+  rlo[e] = r0;
+}
+
+// Outer dimensions from the relative tables, in two passes so that every
+// dimension's loads are in flight together: rel_load fetches each entry's
+// masses and relative origin, rel_place clamps the origin, shifts the masses
+// of a clamped window (zero fill) and leaves dimension 0's in the lane's
+// LDS slot t0.
+template <int I, class SH, class MT>
+__device__ __forceinline__ void rel_load(const DevProblem& P, const InputWalk& iw, const int* j,
+                                         const MT* __restrict__ rm, const int32_t* __restrict__ rlo,
+                                         FixedRow<SH, MT>& R, int* r) {
+  if constexpr (I < SH::N - 1) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < AMY_MAXI; ++k) c += iw.dig[k] * P.rmult[I][k];
+    const int e = P.rel_off[I] + (P.rctx[I] >= 0 ? j[P.rctx[I]] : 0) * P.rcount[I] + c;
+    const MT* tp = rm + (int64_t)e * REL_SLOTS;
+#pragma unroll
+    for (int k = 0; k < SH::L[I]; ++k) R.m[I][k] = tp[k];
+    r[I] = j[I] + rlo[e];
+    rel_load<I + 1, SH, MT>(P, iw, j, rm, rlo, R, r);
+  }
+}
+
+template <int I, class SH, class MT>
+__device__ __forceinline__ void rel_place(const DevProblem& P, const int* r, MT* t0, FixedRow<SH, MT>& R,
+                                          uint32_t& base) {
+  if constexpr (I < SH::N - 1) {
+    constexpr int L = SH::L[I];
+    const int o = min(max(r[I], 0), P.count[I] - L);
+    const int sh = o - r[I];  // slot k holds relative cell k + sh
+    if (sh != 0) {            // window clamped at a grid edge
+      MT w[L];
+#pragma unroll
+      for (int k = 0; k < L; ++k) {
+        w[k] = MT(0);
+#pragma unroll
+        for (int q = 0; q < L; ++q) w[k] = (k + sh == q) ? R.m[I][q] : w[k];
+      }
+#pragma unroll
+      for (int k = 0; k < L; ++k) R.m[I][k] = w[k];
+    }
+    if constexpr (I == 0) {
+#pragma unroll
+      for (int k = 0; k < L; ++k) t0[k * FIX_BLOCK] = R.m[0][k];
+    }
+    base += (uint32_t)o * (uint32_t)P.stride[I];
+    rel_place<I + 1, SH, MT>(P, r, t0, R, base);
+  }
+}
+
+template <int KIND, class SH, int U, class MT, class AT, class VI, class VO, bool COMP>
+__global__ void __launch_bounds__(FIX_BLOCK) k_sweep_rel(DevProblem P, const VI* __restrict__ Vin,
+                                                         VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                                         int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                         const int32_t* __restrict__ rlo) {
+  constexpr int N = SH::N;
+  constexpr int F = N - 1;
+  constexpr int LF = SH::L[F];
+  static_assert(N >= 2 && LF <= U && SH::LMAX <= REL_SLOTS, "relative-table sweep shape");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int fd = P.m - 1, nf = P.ucount[fd], fm = P.rmult[F][fd];
+  // the innermost dimension's tables are the same for every lane: one copy
+  // per block in LDS after the lanes' dimension-0 slots
+  MT* t0 = reinterpret_cast<MT*>(smem) + threadIdx.x;
+  MT* thm = reinterpret_cast<MT*>(smem) + SH::L[0] * FIX_BLOCK;
+  int32_t* thr = reinterpret_cast<int32_t*>(thm + nf * LF);
+  for (int f = threadIdx.x; f < nf; f += FIX_BLOCK) {
+    const int e = P.rel_off[F] + f * fm;
+#pragma unroll
+    for (int k = 0; k < LF; ++k) thm[f * LF + k] = rm[(int64_t)e * REL_SLOTS + k];
+    thr[f] = rlo[e];
+  }
+  __syncthreads();
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * FIX_BLOCK + threadIdx.x;
+  if (s >= (uint32_t)P.n_x) return;
+  const uint8_t lb = label[s];
+  if (lb != LBL_FREE) {
+    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
+    if (pol) pol[s] = -1;
+    return;
+  }
+  int j[N];
+  {
+    uint32_t r = s;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      j[i] = (int)(r % (uint32_t)P.count[i]);
+      r /= (uint32_t)P.count[i];
+    }
+  }
+  const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
+  const int nF = P.count[F];
+  int omin = nF;
+  for (int f = 0; f < nf; ++f) omin = min(omin, min(max(j[F] + thr[f], 0), nF - LF));
+  FixedRow<SH, MT> R;
+  InputWalk iw;
+  iw.reset();
+  AT best = AT(-1);
+  int arg = 0, u = 0;
+  const int nslow = P.n_u / nf;
+  for (int sc = 0; sc < nslow; ++sc) {
+    uint32_t base = (uint32_t)omin;
+    int r[N];
+    rel_load<0, SH, MT>(P, iw, j, rm, rlo, R, r);
+    rel_place<0, SH, MT>(P, r, t0, R, base);
+    AT A[U];
+    contract_fac<SH, U, MT, AT, VI, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
+    for (int f = 0; f < nf; ++f, ++u) {
+      const int g = j[F] + thr[f] - omin;  // A index of the first kept cell
+      AT q = AT(0);
+#pragma unroll
+      for (int k = 0; k < LF; ++k) {
+        const int t = g + k;
+        AT a = A[0];
+#pragma unroll
+        for (int jj = 1; jj < U; ++jj) a = (t == jj) ? A[jj] : a;
+        const bool ok = t >= 0 && t < U && omin + t < nF;
+        const AT qk = fma_(AT(thm[f * LF + k]), a, q);
+        q = ok ? qk : q;
+      }
+      if (q > best) {
+        best = q;
+        arg = u;
+      }
+    }
+#pragma unroll
+    for (int k = AMY_MAXI - 1; k >= 0; --k) {
+      if (k < fd) {
+        if (++iw.dig[k] < P.ucount[k]) break;
+        iw.dig[k] = 0;
+      }
+    }
+  }
+  Vout[s] = VO(best);
+  if (pol) pol[s] = (int16_t)arg;
+}
+
 // ------------------------------------------------------------- launchers
 
 template <int KIND, class SH>
@@ -490,12 +703,12 @@ struct FacLaunch {
   static bool feasible(const DevProblem& P) {
     if (!FixedLaunch<KIND, SH>::matches(P) || P.nocut) return false;
     const int F = SH::N - 1, fd = P.m - 1;
-    if (P.dep_mult[F][fd] <= 0) return false;
+    if (P.rmult[F][fd] <= 0 || P.dep_mult[F][fd] <= 0) return false;
     for (int k = 0; k < fd; ++k)
-      if (P.dep_mult[F][k] != 0) return false;
+      if (P.rmult[F][k] != 0) return false;
     for (int i = 0; i < F; ++i)
-      if (P.dep_mult[i][fd] != 0) return false;
-    if (P.ccount[F] <= 0) return false;
+      if (P.rmult[i][fd] != 0) return false;
+    if (P.ccount[F] <= 0 || P.ucount[fd] > 1024) return false;
     return span_bound(P) <= U;
   }
   // Window origins move by at most ceil(drift range / h) cells over the fast
@@ -503,8 +716,21 @@ struct FacLaunch {
   static int span_bound(const DevProblem& P);
   template <class MT, class AT, class VI, class VO, bool COMP>
   static void go(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
-                 unsigned long long* tailmax, hipStream_t st) {
+                 unsigned long long* tailmax, const void* rel, hipStream_t st) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
+    if constexpr (RelDrift<KIND, SH::N>::ok) {
+      if (!tailmax && rel && P.rel_entries > 0) {
+        const MT* rm = (const MT*)rel;
+        const int32_t* ro = (const int32_t*)((const char*)rel +
+                                             (((uint64_t)P.rel_entries * REL_SLOTS * sizeof(MT) + 255) & ~255ull));
+        const int nf = P.ucount[P.m - 1];
+        const size_t lds = (size_t)SH::L[0] * sizeof(MT) * FIX_BLOCK + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) +
+                           (size_t)nf * 4;
+        hipLaunchKernelGGL((k_sweep_rel<KIND, SH, U, MT, AT, VI, VO, COMP>), g, b, lds, st, P, (const VI*)Vin,
+                           (VO*)Vout, label, pol, rm, ro);
+        return;
+      }
+    }
     // the block's tables, then one slot of dimension 0's masses per lane
     const uint32_t t0 = (uint32_t)(((tailmax ? P.lds_bytes_tail : P.lds_bytes_fixed) + 15) & ~15);
     const size_t lds = t0 + (size_t)SH::L[0] * sizeof(MT) * FIX_BLOCK;
@@ -516,13 +742,43 @@ struct FacLaunch {
                          (const VI*)Vin, (VO*)Vout, label, pol, tailmax, t0);
   }
   static hipError_t sweep(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout, const uint8_t* label,
-                          int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
+                          int16_t* pol, unsigned long long* tailmax, const void* rel, hipStream_t st) {
     switch (sk) {
-      case SWEEP_F64: go<double, double, double, double, false>(P, Vin, Vout, label, pol, tailmax, st); break;
-      case SWEEP_F32: go<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, st); break;
-      case SWEEP_F32_LAST: go<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, st); break;
+      case SWEEP_F64: go<double, double, double, double, false>(P, Vin, Vout, label, pol, tailmax, rel, st); break;
+      case SWEEP_F32: go<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, rel, st); break;
+      case SWEEP_F32_LAST:
+        go<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, rel, st);
+        break;
     }
     return hipGetLastError();
+  }
+  // shared relative tables of the family, if it has them
+  static int rel_plan(DevProblem& P) {
+    if constexpr (!RelDrift<KIND, SH::N>::ok) {
+      return 0;
+    } else {
+      int off = 0;
+      for (int i = 0; i < SH::N; ++i) {
+        const int cx = RelDrift<KIND, SH::N>::ctx(i);
+        P.rctx[i] = cx;
+        P.rel_off[i] = off;
+        off += (cx >= 0 ? P.count[cx] : 1) * P.rcount[i];
+      }
+      P.rel_entries = off;
+      return off;
+    }
+  }
+  static hipError_t rel_build(const DevProblem& P, bool f64, void* rel, hipStream_t st) {
+    if constexpr (RelDrift<KIND, SH::N>::ok) {
+      const dim3 g((unsigned)((P.rel_entries + 63) / 64)), b(64);
+      const uint64_t msz = f64 ? 8 : 4;
+      int32_t* ro = (int32_t*)((char*)rel + (((uint64_t)P.rel_entries * REL_SLOTS * msz + 255) & ~255ull));
+      if (f64) hipLaunchKernelGGL((k_rel_build<KIND, SH::N, double>), g, b, 0, st, P, (double*)rel, ro);
+      else hipLaunchKernelGGL((k_rel_build<KIND, SH::N, float>), g, b, 0, st, P, (float*)rel, ro);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
 };
 
@@ -560,9 +816,27 @@ bool amy_fac_available(const DevProblem& P) {
 }
 
 hipError_t amy_launch_sweep_fac(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
-                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
+                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax, const void* rel,
+                                hipStream_t st) {
+#define X(K, SH, U)                            \
+  if (FacLaunch<K, SH, U>::feasible(P)) \
+    return FacLaunch<K, SH, U>::sweep(P, sk, Vin, Vout, label, pol, tailmax, rel, st);
+  AMY_FAC_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int amy_rel_plan(DevProblem& P) {
 #define X(K, SH, U) \
-  if (FacLaunch<K, SH, U>::feasible(P)) return FacLaunch<K, SH, U>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+  if (FacLaunch<K, SH, U>::feasible(P)) return FacLaunch<K, SH, U>::rel_plan(P);
+  AMY_FAC_SHAPES(X)
+#undef X
+  return 0;
+}
+
+hipError_t amy_launch_rel_build(const DevProblem& P, bool f64, void* rel, hipStream_t st) {
+#define X(K, SH, U) \
+  if (FacLaunch<K, SH, U>::feasible(P)) return FacLaunch<K, SH, U>::rel_build(P, f64, rel, st);
   AMY_FAC_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

@@ -229,6 +229,18 @@ static amy_status plan_tables(const amy_problem* p, Plan* pl) {
       eu += D.L[i];
     }
   }
+  for (int i = 0; i < n; ++i) {
+    D.rcount[i] = C[i];
+    int mult = 1;
+    for (int k = m - 1; k >= 0; --k) {
+      D.rmult[i][k] = 0;
+      if (dep[i] >> k & 1u) {
+        D.rmult[i][k] = mult;
+        mult *= D.ucount[k];
+      }
+    }
+    for (int k = m; k < AMY_MAXI; ++k) D.rmult[i][k] = 0;
+  }
   if (D.lds_bytes_tail > LDS_BUDGET)
     return amy_fail(AMY_E_UNSUPPORTED, "window tables need %d B of LDS per 64 lanes (> %d)", D.lds_bytes_tail,
                     LDS_BUDGET);
@@ -400,6 +412,16 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
                       (long long)(sum_l * msz));
   }
   pl->dev.variant = v;
+  pl->dev.rel_entries = 0;
+  if (v == AMY_VARIANT_FACTORED && amy_rel_plan(pl->dev) > 0) {
+    // relative tables after the rest of the workspace: masses, then origins
+    const uint64_t msz = pl->f64 ? 8 : 4, ne = (uint64_t)pl->dev.rel_entries;
+    pl->off_rel = pl->ws_bytes;
+    pl->ws_bytes += ((ne * 8 * msz + 255) & ~255ull) + ((ne * 4 + 255) & ~255ull);
+    if (budget && pl->ws_bytes > budget)
+      return amy_fail(AMY_E_NOMEM, "workspace %llu B exceeds budget %llu B",
+                      (unsigned long long)pl->ws_bytes, (unsigned long long)budget);
+  }
   plan_group(pl, v == AMY_VARIANT_GROUP64 ? 64 : 16);
   if (v != AMY_VARIANT_GROUP16 && v != AMY_VARIANT_GROUP64) pl->dev.grp_g = 1;
   return AMY_OK;
@@ -454,10 +476,19 @@ hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_
   if (pl.mode == AMY_MODE_STORED)
     return amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
                                    label, pk, st);
-  if (D.variant == AMY_VARIANT_FACTORED) return amy_launch_sweep_fac(D, sk, Vb[cur], out, label, pk, tail, st);
+  if (D.variant == AMY_VARIANT_FACTORED)
+    return amy_launch_sweep_fac(D, sk, Vb[cur], out, label, pk, tail, D.rel_entries > 0 ? base + pl.off_rel : nullptr,
+                                st);
   if (D.variant == AMY_VARIANT_FIXED) return amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk, tail, st);
   if (D.grp_g > 1) return amy_launch_sweep_group(D, sk, Vb[cur], out, label, pk, tail, st);
   return amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk, tail, st);
+}
+
+// Per-solve tables that the sweeps read (the factored sweep's shared
+// relative tables), after the labels and before the first step.
+hipError_t amy_enqueue_prepare(const Plan& pl, hipStream_t st, void* ws, int horizon) {
+  if (pl.dev.rel_entries <= 0 || horizon < 1) return hipSuccess;
+  return amy_launch_rel_build(pl.dev, pl.f64, (char*)ws + pl.off_rel, st);
 }
 
 amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol,
@@ -476,6 +507,7 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
   if (want_tail && horizon == 0 && (e = amy_launch_tail(D, label, tailmax, st)) != hipSuccess)
     return amy_hip_fail(e, "tail kernel");
   const bool stored = (pl.mode == AMY_MODE_STORED);
+  if ((e = amy_enqueue_prepare(pl, st, ws, horizon)) != hipSuccess) return amy_hip_fail(e, "table kernel");
   if (stored && horizon > 0) {
     if ((e = amy_launch_build(D, pl.f64, label, base + pl.off_T, (int32_t*)(base + pl.off_org),
                               want_tail ? tailmax : nullptr, st)) != hipSuccess)

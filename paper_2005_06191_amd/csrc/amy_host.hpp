@@ -13,6 +13,7 @@ struct Plan {
   bool f64;         // FP64 path
   int mode;         // resolved amy_mode
   uint64_t off_label, off_v0, off_v1, off_tail, off_T, off_org;
+  uint64_t off_rel;  // factored sweep's shared relative tables (dev.rel_entries > 0)
   uint64_t stored_bytes, ws_bytes;
 };
 
@@ -31,6 +32,7 @@ void amy_layout(Plan* pl, int mode);
 amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl);
 amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
                        bool want_tail, Timing* tm);
+hipError_t amy_enqueue_prepare(const Plan& pl, hipStream_t st, void* ws, int horizon);
 hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
                             int k, bool want_tail);
 

@@ -38,6 +38,11 @@ hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void*
                                   const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
                                   hipStream_t st);
 // Factored compiled-shape sweep (inputs sharing the outer dimensions' windows).
+// rel: the shared relative tables (when P.rel_entries > 0) for the steps
+// without the FP64 tail; the tail step builds its tables per state.
 bool amy_fac_available(const DevProblem& P);
+int amy_rel_plan(DevProblem& P);
+hipError_t amy_launch_rel_build(const DevProblem& P, bool f64, void* rel, hipStream_t st);
 hipError_t amy_launch_sweep_fac(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
-                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax, hipStream_t st);
+                                const uint8_t* label, int16_t* pol, unsigned long long* tailmax, const void* rel,
+                                hipStream_t st);

@@ -29,6 +29,19 @@ struct DevProblem {
   // ccount[i] == 0: the table is rebuilt inside the loop when mu_i changes.
   int32_t dep_mult[AMY_MAXD][AMY_MAXI];
   int32_t ccount[AMY_MAXD];
+  // The same numbering for every dimension, cached or not: table c of
+  // dimension i for digits d is c = sum_k d_k rmult[i][k], of rcount[i].
+  int32_t rmult[AMY_MAXD][AMY_MAXI];
+  int32_t rcount[AMY_MAXD];
+  // Shared relative tables (factored sweep of a family whose mean in
+  // dimension i, minus the state's own cell centre, depends only on the
+  // inputs and on the state's cell centre in dimension rctx[i], or on the
+  // inputs alone when rctx[i] < 0): entry j * rcount[i] + c + rel_off[i]
+  // holds the 1-D masses of the kept cells relative to the state's cell
+  // (zero past the kept count) and their first cell's relative index.
+  int32_t rctx[AMY_MAXD];
+  int32_t rel_off[AMY_MAXD];
+  int32_t rel_entries;        // 0: no relative tables
   int32_t toff[AMY_MAXD];     // first LDS table entry of dimension i
   int32_t ooff[AMY_MAXD];     // first cached-origin slot of dimension i
   int32_t lds_int_off;        // byte offset of the origin slots in a block's LDS

@@ -266,6 +266,7 @@ void amy_server::run() {
       hipError_t e = amy_launch_init(pl.dev, (uint8_t*)(b + pl.off_label), b + pl.off_v0, pl.f64,
                                      r->prob.horizon == 0 ? vout : nullptr,
                                      (unsigned long long*)(b + pl.off_tail), stream);
+      if (e == hipSuccess) e = amy_enqueue_prepare(pl, stream, b, r->prob.horizon);
       if (e == hipSuccess && pl.mode == AMY_MODE_STORED && r->prob.horizon > 0)
         e = amy_launch_build(pl.dev, pl.f64, (const uint8_t*)(b + pl.off_label), b + pl.off_T,
                              (int32_t*)(b + pl.off_org), (unsigned long long*)(b + pl.off_tail), stream);
@@ -451,8 +452,10 @@ extern "C" amy_status amy_server_submit(amy_server* s, const amy_problem* p, int
   // launch per step; the rest share the batched step, which runs the
   // run-time-window code (same bits as the compiled-shape sweep)
   r->solo = r->plan.dev.n_x >= SOLO_STATES || !amy_batch_supports(r->plan.dev.kind, r->plan.dev.n, r->plan.mode);
-  if (!r->solo && (r->plan.dev.variant == AMY_VARIANT_FIXED || r->plan.dev.variant == AMY_VARIANT_FACTORED))
+  if (!r->solo && (r->plan.dev.variant == AMY_VARIANT_FIXED || r->plan.dev.variant == AMY_VARIANT_FACTORED)) {
     r->plan.dev.variant = AMY_VARIANT_LANES;
+    r->plan.dev.rel_entries = 0;
+  }
   r->off_v = al256(r->plan.ws_bytes);
   r->off_pol = al256(r->off_v + (uint64_t)r->plan.dev.n_x * 8);
   r->bytes = r->off_pol + (r->want_policy ? al256((uint64_t)p->horizon * r->plan.dev.n_x * 2) : 0);

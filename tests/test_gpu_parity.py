@@ -224,6 +224,28 @@ def test_factored_sweep_matches_oracle_and_fixed(orc, name):
     assert a.info["max_row_tail"] == b.info["max_row_tail"]
 
 
+def test_factored_shared_tables_edges(orc):
+    """The steps after the first read shared relative tables: states whose
+    windows are clipped at every grid edge (a patch on which x, y and the
+    heading all reach both ends), with and without the tail step, match the
+    oracle; T_d = 1 without info uses the shared tables on its only step."""
+    import paper_2005_06191_amd as A
+    p = _uni_small(precision="fp32").with_(horizon=5, spec="safety")
+    say("[factored] shared tables at the grid edges")
+    assert A.query(p)["variant"] == "factored"
+    ref = orc.solve(p, gap=True)
+    r = A.solve(p, variant="factored", info=True)
+    compare(p, ref, r.V.cpu().numpy(), r.policy.cpu().numpy(), TOL_FP32, gap=ref["gap"])
+    r2 = A.solve(p, variant="factored", info=False)
+    compare(p, ref, r2.V.cpu().numpy(), None, TOL_FP32)
+    q = p.with_(horizon=1)
+    r1 = A.solve(q, variant="factored", info=False, policy=False)
+    compare(q, orc.solve(q), r1.V.cpu().numpy(), None, TOL_FP32)
+    q64 = p.with_(precision="fp64", horizon=3)
+    r64 = A.solve(q64, variant="factored", info=False, policy=False)
+    compare(q64, orc.solve(q64), r64.V.cpu().numpy(), None, TOL_FP64)
+
+
 def test_factored_full_size_vs_fixed():
     import paper_2005_06191_amd as A
     p = W.unicycle3d().with_(horizon=6)

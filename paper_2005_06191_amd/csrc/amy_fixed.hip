@@ -64,6 +64,28 @@ __device__ __forceinline__ double VBuf<double>::load(uint32_t voff, uint32_t sof
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
+// n consecutive values from byte offset voff + soff into v[0 .. n), in
+// 8-byte loads where they fit.  (This compiler lowers the 96- and 128-bit
+// raw buffer load builtins, and element access on the 64-bit one's vector
+// result, to a single dword load; only whole-value casts of the 64-bit
+// load are used.)
+template <class VT, int n>
+__device__ __forceinline__ void vbuf_run(const VBuf<VT>& vb, uint32_t voff, uint32_t soff, VT* v) {
+  int t = 0;
+  if constexpr (sizeof(VT) == 4) {
+#pragma unroll
+    for (; t + 2 <= n; t += 2) {
+      // whole-value cast: extracting the builtin's vector elements is also miscompiled
+      const uint64_t q = __builtin_bit_cast(
+          uint64_t, __builtin_amdgcn_raw_buffer_load_b64(vb.r, (int)(voff + (uint32_t)(t * 4)), (int)soff, 0));
+      v[t] = __builtin_bit_cast(float, (uint32_t)q);
+      v[t + 1] = __builtin_bit_cast(float, (uint32_t)(q >> 32));
+    }
+  }
+#pragma unroll
+  for (; t < n; ++t) v[t] = vb.load(voff + (uint32_t)(t * sizeof(VT)), soff);
+}
+
 // 1-D masses of an L-slot window into registers (same edges as dim_table).
 template <class MT, int L>
 __device__ __forceinline__ void fixed_table(const DevProblem& P, int i, const Win& w, MT* m) {
@@ -264,8 +286,10 @@ __device__ __forceinline__ void contract_fac_in(const FixedRow<SH, MT>& R, const
     const uint32_t sk = soff + (uint32_t)k * (uint32_t)stride[D] * (uint32_t)sizeof(VT);
     AT inner[U];
     if constexpr (D == SH::N - 2) {
+      VT v[U];
+      vbuf_run<VT, U>(vb, voff, sk, v);
 #pragma unroll
-      for (int t = 0; t < U; ++t) inner[t] = AT(vb.load(voff + (uint32_t)(t * sizeof(VT)), sk));
+      for (int t = 0; t < U; ++t) inner[t] = AT(v[t]);
     } else {
       contract_fac_in<D + 1, SH, U, MT, AT, VT>(R, vb, voff, sk, stride, inner);
     }

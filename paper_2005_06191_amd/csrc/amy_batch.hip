@@ -22,45 +22,28 @@
 
 #define BATCH_BLOCK 64
 
-// The (dynamics, dimension) pairs a batched launch can hold.
-#define AMY_BATCH_FAMILIES(X)                                                                    \
+// The (dynamics, dimension) pairs a batched launch can hold, in two sets:
+// the 2-D / 3-D set of the batch workload and every built-in family.  Each
+// launch is instantiated for one set, so a batch of small systems does not
+// carry the register budget of the 5-D and 7-D code.
+#define AMY_BATCH_FAMILIES_SMALL(X)                                                              \
   X(AMY_DYN_AFFINE_, 1) X(AMY_DYN_AFFINE_, 2) X(AMY_DYN_AFFINE_, 3) X(AMY_DYN_AFFINE_, 4)         \
-  X(AMY_DYN_UNICYCLE_, 3) X(AMY_DYN_ROOM_, 2) X(AMY_DYN_ROOM_, 3) X(AMY_DYN_ROOM_, 4)             \
-  X(AMY_DYN_ROOM_, 5) X(AMY_DYN_VEHICLE7_, 7)
+  X(AMY_DYN_UNICYCLE_, 3)
+#define AMY_BATCH_FAMILIES(X)                                                                    \
+  AMY_BATCH_FAMILIES_SMALL(X)                                                                    \
+  X(AMY_DYN_ROOM_, 2) X(AMY_DYN_ROOM_, 3) X(AMY_DYN_ROOM_, 4) X(AMY_DYN_ROOM_, 5) X(AMY_DYN_VEHICLE7_, 7)
 
-// Out-of-line entry to the single-system per-state code, so that each
-// (family, dimension, precision) instance gets its own register
-// allocation inside the batched kernels.
-template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
-__device__ __noinline__ void tile_call(const DevProblem& P, uint32_t s, const VI* Vin, VO* Vout,
-                                       const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
-                                       unsigned char* smem) {
-  sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
-}
-
-template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G>
-__device__ __noinline__ void group_call(const DevProblem& P, uint32_t tile, const VI* Vin, VO* Vout,
-                                        const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
-                                        unsigned char* smem) {
-  sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, tile, Vin, Vout, label, pol, tailmax, smem);
-}
-
-template <int N, class MT, class AT, class VI, class VO, bool COMP>
-__device__ __noinline__ void stored_call(const DevProblem& P, uint32_t s, const MT* T, const int32_t* org,
-                                         const VI* Vin, VO* Vout, const uint8_t* label, int16_t* pol) {
-  stored_tile<N, MT, AT, VI, VO, COMP>(P, s, T, org, Vin, Vout, label, pol);
-}
-
-// Calls the per-state code of variant LANES (G == 1: s is the state) or of
-// a group variant (G lanes per state: s is the tile of 64/G states).
+// Every per-state call below is inlined: the system descriptor is then read
+// through a wave-uniform index, so its fields live in scalar registers (an
+// out-of-line call would see them as per-lane values).
 template <int KIND, int N, int G, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
 __device__ __forceinline__ void call_variant(const DevProblem& P, uint32_t s, const VI* Vin, VO* Vout,
                                              const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
                                              unsigned char* smem) {
   if constexpr (G == 1)
-    tile_call<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
+    sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
   else
-    group_call<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, s, Vin, Vout, label, pol, tailmax, smem);
+    sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, s, Vin, Vout, label, pol, tailmax, smem);
 }
 
 template <int KIND, int N, int G, bool F64>
@@ -104,41 +87,46 @@ __device__ __forceinline__ void run_stored(const BatchSys& B, uint32_t s, int t)
   const bool last = (k == 1);
   int16_t* pol = B.pol ? B.pol + (int64_t)(k - 1) * P.n_x : nullptr;
   if constexpr (F64) {
-    stored_call<N, double, double, double, double, false>(P, s, (const double*)B.T, B.org,
+    stored_tile<N, double, double, double, double, false>(P, s, (const double*)B.T, B.org,
                                                           (const double*)((t & 1) ? B.V1 : B.V0),
                                                           last ? B.Vout : (double*)((t & 1) ? B.V0 : B.V1),
                                                           B.label, pol);
   } else if (last) {
-    stored_call<N, float, double, float, double, false>(P, s, (const float*)B.T, B.org,
+    stored_tile<N, float, double, float, double, false>(P, s, (const float*)B.T, B.org,
                                                         (const float*)((t & 1) ? B.V1 : B.V0), B.Vout, B.label, pol);
   } else {
-    stored_call<N, float, float, float, float, true>(P, s, (const float*)B.T, B.org,
+    stored_tile<N, float, float, float, float, true>(P, s, (const float*)B.T, B.org,
                                                      (const float*)((t & 1) ? B.V1 : B.V0),
                                                      (float*)((t & 1) ? B.V0 : B.V1), B.label, pol);
   }
 }
 
-// One tile of system B at its local step t (0 = the step k = T_d).
-template <bool F64>
+// One tile of system B at its local step t (0 = the step k = T_d).  FS: the
+// family set compiled in (0: 2-D / 3-D, 1: all); STORED: stored rows too.
+template <bool F64, int FS, bool STORED>
 __device__ __forceinline__ void run_tile(const BatchSys& B, uint32_t tile, int t, unsigned char* smem) {
   const uint32_t s = tile * BATCH_BLOCK + (threadIdx.x & 63);
-  if (B.mode == 1) {  // AMY_MODE_STORED: rows were built at admission
-    switch (B.P.n) {
-      case 1: run_stored<1, F64>(B, s, t); return;
-      case 2: run_stored<2, F64>(B, s, t); return;
-      case 3: run_stored<3, F64>(B, s, t); return;
-      case 4: run_stored<4, F64>(B, s, t); return;
-      case 5: run_stored<5, F64>(B, s, t); return;
-      case 7: run_stored<7, F64>(B, s, t); return;
+  if constexpr (STORED) {
+    if (B.mode == 1) {  // AMY_MODE_STORED: rows were built at admission
+      switch (B.P.n) {
+        case 1: run_stored<1, F64>(B, s, t); return;
+        case 2: run_stored<2, F64>(B, s, t); return;
+        case 3: run_stored<3, F64>(B, s, t); return;
+        case 4: run_stored<4, F64>(B, s, t); return;
+        case 5: run_stored<5, F64>(B, s, t); return;
+        case 7: run_stored<7, F64>(B, s, t); return;
+      }
+      return;
     }
-    return;
   }
-  switch (B.P.kind * 16 + B.P.n) {
 #define X(K, N_) \
   case K * 16 + N_: run_otf<K, N_, F64>(B, tile, t, smem); return;
-    AMY_BATCH_FAMILIES(X)
-#undef X
+  if constexpr (FS == 0) {
+    switch (B.P.kind * 16 + B.P.n) { AMY_BATCH_FAMILIES_SMALL(X) }
+  } else {
+    switch (B.P.kind * 16 + B.P.n) { AMY_BATCH_FAMILIES(X) }
   }
+#undef X
 }
 
 bool amy_batch_supports(int kind, int n, int mode) {
@@ -148,6 +136,14 @@ bool amy_batch_supports(int kind, int n, int mode) {
   AMY_BATCH_FAMILIES(X)
 #undef X
   return false;
+}
+
+int amy_batch_family_set(int kind, int n) {
+#define X(K, N_) \
+  if (kind == K && n == N_) return 0;
+  AMY_BATCH_FAMILIES_SMALL(X)
+#undef X
+  return 1;
 }
 
 template <bool F64>
@@ -170,32 +166,34 @@ __device__ __forceinline__ int find_sys(const int32_t* __restrict__ tprefix, int
     if ((uint32_t)tprefix[mid] <= item) lo = mid;
     else hi = mid - 1;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);  // item is wave-uniform, so is the system
 }
 
-// Grid-wide barrier over nblocks co-resident workgroups.  Agent-scope
-// fences publish each workgroup's V writes to every XCD before the
-// generation advances.  Bounded wait: on timeout the error flag is set.
+// Grid-wide barrier over nblocks co-resident workgroups.  Arrival is an
+// acquire-release add (publishes this workgroup's V writes); the waiters
+// poll the generation with relaxed loads and a sleep between polls -- an
+// acquire load per poll would invalidate the local caches every time, and
+// thousands of polling waves would starve the working ones -- and take one
+// acquire fence when it moves.  Bounded wait: on timeout the error flag is
+// set and the wave carries on, so the grid always drains.
 __device__ __forceinline__ void grid_barrier(BatchCtl* ctl, unsigned nblocks, unsigned& gen) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned a = atomicAdd(&ctl->bar_count, 1u);
+    const unsigned a = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (a == nblocks - 1) {
-      atomicExch(&ctl->bar_count, 0u);
-      __threadfence();
-      atomicAdd(&ctl->bar_gen, 1u);
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1u << 25)) {
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(8);
+        if (++spins > (1u << 24)) {
           atomicOr(&ctl->err, 1u);
           break;
         }
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   ++gen;
   __syncthreads();
@@ -211,7 +209,7 @@ __device__ __forceinline__ bool grab(BatchCtl* ctl, int phase, uint32_t nitems, 
     const uint32_t lo = xcd_order ? (uint32_t)(((uint64_t)nitems * qq) / 8) : 0u;
     const uint32_t hi = xcd_order ? (uint32_t)(((uint64_t)nitems * (qq + 1)) / 8) : nitems;
     if ((threadIdx.x & 63) == 0) v = atomicAdd(&ctl->ctr[phase * 8 + qq], (unsigned)chunk);
-    v = __shfl(v, 0);
+    v = __builtin_amdgcn_readfirstlane(v);  // wave-uniform from here on
     if (lo + v < hi) {
       first = lo + v;
       last = min(hi, first + (uint32_t)chunk);
@@ -223,8 +221,8 @@ __device__ __forceinline__ bool grab(BatchCtl* ctl, int phase, uint32_t nitems, 
   return false;
 }
 
-template <bool F64>
-__global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) k_batch_persistent(const BatchSys* __restrict__ sys, int nsys,
+template <bool F64, int FS>
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_persistent(const BatchSys* __restrict__ sys, int nsys,
                                                                   const int32_t* __restrict__ tprefix,
                                                                   const int32_t* __restrict__ active,
                                                                   int max_steps, BatchCtl* ctl, int chunk,
@@ -242,7 +240,7 @@ __global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_e
         const BatchSys& B = sys[j];
         const uint32_t tile = it - (uint32_t)tprefix[j];
         if (phase == 0) init_tile<F64>(B, tile);
-        else run_tile<F64>(B, tile, phase - 1, smem);
+        else run_tile<F64, FS, false>(B, tile, phase - 1, smem);
       }
     }
     if (phase < max_steps) grid_barrier(ctl, gridDim.x, gen);
@@ -254,9 +252,9 @@ __global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_e
 // BatchSys::step_base holds each system's local step t for this launch.
 // Both are read from device memory, so one captured launch serves any set
 // of active systems.  Items are dealt by a fixed stride (no counters).
-template <bool F64>
-__global__ void __launch_bounds__(BATCH_BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8)))
-k_batch_step(const BatchSys* __restrict__ sys, const int32_t* __restrict__ meta) {
+template <bool F64, int FS>
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(const BatchSys* __restrict__ sys,
+                                                            const int32_t* __restrict__ meta) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nsys = meta[0];
   const int32_t* tprefix = meta + 1;
@@ -265,7 +263,7 @@ k_batch_step(const BatchSys* __restrict__ sys, const int32_t* __restrict__ meta)
     const int j = find_sys(tprefix, nsys, it);
     const BatchSys& B = sys[j];
     if (B.step_base < 0 || B.step_base >= B.horizon) continue;
-    run_tile<F64>(B, it - (uint32_t)tprefix[j], B.step_base, smem);
+    run_tile<F64, FS, true>(B, it - (uint32_t)tprefix[j], B.step_base, smem);
   }
 }
 
@@ -286,27 +284,35 @@ __global__ void k_fill_u32(unsigned* p, size_t n) {
 
 // ------------------------------------------------------------- launchers
 
-const void* amy_batch_persistent_kernel(bool f64) {
-  return f64 ? (const void*)&k_batch_persistent<true> : (const void*)&k_batch_persistent<false>;
+const void* amy_batch_persistent_kernel(bool f64, int fs) {
+  if (fs == 0) return f64 ? (const void*)&k_batch_persistent<true, 0> : (const void*)&k_batch_persistent<false, 0>;
+  return f64 ? (const void*)&k_batch_persistent<true, 1> : (const void*)&k_batch_persistent<false, 1>;
 }
 
-hipError_t amy_launch_batch_persistent(bool f64, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
+hipError_t amy_launch_batch_persistent(bool f64, int fs, unsigned grid, size_t lds, const BatchSys* sys, int nsys,
                                        const int32_t* tprefix, const int32_t* active, int max_steps,
                                        BatchCtl* ctl, int chunk, int xcd_order, hipStream_t st) {
   void* args[] = {(void*)&sys, (void*)&nsys, (void*)&tprefix, (void*)&active, (void*)&max_steps,
                   (void*)&ctl, (void*)&chunk, (void*)&xcd_order};
-  return hipLaunchCooperativeKernel(amy_batch_persistent_kernel(f64), dim3(grid), dim3(BATCH_BLOCK), args,
+  return hipLaunchCooperativeKernel(amy_batch_persistent_kernel(f64, fs), dim3(grid), dim3(BATCH_BLOCK), args,
                                     (unsigned)lds, st);
 }
 
-const void* amy_batch_step_kernel(bool f64) {
-  return f64 ? (const void*)&k_batch_step<true> : (const void*)&k_batch_step<false>;
+const void* amy_batch_step_kernel(bool f64, int fs) {
+  if (fs == 0) return f64 ? (const void*)&k_batch_step<true, 0> : (const void*)&k_batch_step<false, 0>;
+  return f64 ? (const void*)&k_batch_step<true, 1> : (const void*)&k_batch_step<false, 1>;
 }
 
-hipError_t amy_launch_batch_step(bool f64, unsigned grid, size_t lds, const BatchSys* sys, const int32_t* meta,
-                                 hipStream_t st) {
-  if (f64) hipLaunchKernelGGL((k_batch_step<true>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, meta);
-  else hipLaunchKernelGGL((k_batch_step<false>), dim3(grid), dim3(BATCH_BLOCK), lds, st, sys, meta);
+hipError_t amy_launch_batch_step(bool f64, int fs, unsigned grid, size_t lds, const BatchSys* sys,
+                                 const int32_t* meta, hipStream_t st) {
+  const dim3 g(grid), b(BATCH_BLOCK);
+  if (fs == 0) {
+    if (f64) hipLaunchKernelGGL((k_batch_step<true, 0>), g, b, lds, st, sys, meta);
+    else hipLaunchKernelGGL((k_batch_step<false, 0>), g, b, lds, st, sys, meta);
+  } else {
+    if (f64) hipLaunchKernelGGL((k_batch_step<true, 1>), g, b, lds, st, sys, meta);
+    else hipLaunchKernelGGL((k_batch_step<false, 1>), g, b, lds, st, sys, meta);
+  }
   return hipGetLastError();
 }
 

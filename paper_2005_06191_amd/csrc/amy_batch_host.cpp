@@ -20,6 +20,7 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
   bp.plans.assign(count, Plan());
   bp.lds = 0;
   bp.maxT = 0;
+  bp.fs = 0;
   for (int i = 0; i < count; ++i) {
     amy_status st = amy_validate(&probs[i]);
     if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
@@ -46,6 +47,7 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
     if (probs[i].horizon > AMY_BATCH_MAX_STEPS)
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: horizon %d > %d", i, probs[i].horizon, AMY_BATCH_MAX_STEPS);
     bp.maxT = std::max(bp.maxT, (int)probs[i].horizon);
+    bp.fs = std::max(bp.fs, amy_batch_family_set(D.kind, D.n));
     bp.lds = std::max(bp.lds, (size_t)(D.grp_g > 1 ? D.lds_bytes_group : D.lds_bytes_tail));
   }
   // longest horizon first: the systems still running at global step s are a prefix
@@ -127,7 +129,7 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
   int dev = 0, ncu = 0, occ = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_persistent_kernel(bp.f64), 64, bp.lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_persistent_kernel(bp.f64, bp.fs), 64, bp.lds);
   if (e != hipSuccess || occ < 1) return amy_hip_fail(e, "batch occupancy query");
   const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
   const unsigned grid = (unsigned)std::max(1, ncu * bpc);
@@ -137,7 +139,7 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
     hipEventCreate(&ev[1]);
     hipEventRecord(ev[0], hs);
   }
-  e = amy_launch_batch_persistent(bp.f64, grid, bp.lds, (const BatchSys*)(ws + bp.off_sys), count,
+  e = amy_launch_batch_persistent(bp.f64, bp.fs, grid, bp.lds, (const BatchSys*)(ws + bp.off_sys), count,
                                   (const int32_t*)(ws + bp.off_tp), (const int32_t*)(ws + bp.off_act), bp.maxT,
                                   (BatchCtl*)(ws + bp.off_ctl), std::max(1, tune.chunk), tune.xcd_order, hs);
   if (e != hipSuccess) {

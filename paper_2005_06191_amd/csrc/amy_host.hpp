@@ -49,6 +49,7 @@ struct BatchPlan {
   std::vector<int32_t> active;    // systems still running at each global step
   bool f64 = false;
   int maxT = 0;
+  int fs = 0;                     // family set compiled into the launch (0: 2-D / 3-D, 1: all)
   size_t lds = 0;                 // dynamic LDS of the launch
   uint64_t off_sys = 0, off_tp = 0, off_act = 0, off_ctl = 0, ws_bytes = 0;
   std::vector<uint64_t> base;     // per system (input order): its region
@@ -56,7 +57,7 @@ struct BatchPlan {
 
 // Launch parameters of the persistent batched kernel chosen by the tuner.
 struct BatchTune {
-  int chunk = 1;          // tiles taken per work-queue grab
+  int chunk = 4;          // tiles taken per work-queue grab
   int blocks_per_cu = 0;  // resident workgroups per CU (0: as many as fit)
   int xcd_order = 1;      // one work queue per XCD over a contiguous tile range
 };

@@ -140,7 +140,7 @@ struct amy_server {
   int32_t* d_meta[2] = {nullptr, nullptr};
   BatchSys* h_sys[2] = {nullptr, nullptr};
   int32_t* h_meta[2] = {nullptr, nullptr};
-  std::map<int, hipGraphExec_t> graphs[2];  // LDS tier -> captured step
+  std::map<int, hipGraphExec_t> graphs[2];  // family set * 2^20 + LDS tier -> captured step
   std::mutex mu;
   std::condition_variable cv, cv_done;
   std::deque<Request*> queue;
@@ -155,7 +155,7 @@ struct amy_server {
   double row_updates = 0, busy_s = 0;
   std::vector<double> lat_ms;
 
-  amy_status step_graph(int prec, int tier, hipGraphExec_t* out);
+  amy_status step_graph(int prec, int fs, int tier, hipGraphExec_t* out);
   void run();
   void fail_active(const char* what, hipError_t e);
   void retire(Request* r);
@@ -164,14 +164,15 @@ struct amy_server {
 
 static const int LDS_TIERS[] = {16 * 1024, 32 * 1024, 48 * 1024, 64 * 1024};
 
-amy_status amy_server::step_graph(int prec, int tier, hipGraphExec_t* out) {
-  auto it = graphs[prec].find(tier);
+amy_status amy_server::step_graph(int prec, int fs, int tier, hipGraphExec_t* out) {
+  const int key = (fs << 20) + tier;
+  auto it = graphs[prec].find(key);
   if (it != graphs[prec].end()) {
     *out = it->second;
     return AMY_OK;
   }
   int occ = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_step_kernel(prec == 1), 64, tier);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_step_kernel(prec == 1, fs), 64, tier);
   if (e != hipSuccess || occ < 1) return amy_hip_fail(e, "server step occupancy");
   const unsigned grid = (unsigned)(ncu * occ);
   hipGraph_t g = nullptr;
@@ -181,12 +182,12 @@ amy_status amy_server::step_graph(int prec, int tier, hipGraphExec_t* out) {
     return amy_hip_fail(e, "server capture");
   hipMemcpyAsync(d_sys[prec], h_sys[prec], sizeof(BatchSys) * cap, hipMemcpyHostToDevice, stream);
   hipMemcpyAsync(d_meta[prec], h_meta[prec], sizeof(int32_t) * (cap + 2), hipMemcpyHostToDevice, stream);
-  amy_launch_batch_step(prec == 1, grid, tier, d_sys[prec], d_meta[prec], stream);
+  amy_launch_batch_step(prec == 1, fs, grid, tier, d_sys[prec], d_meta[prec], stream);
   if ((e = hipStreamEndCapture(stream, &g)) != hipSuccess) return amy_hip_fail(e, "server capture end");
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) return amy_hip_fail(e, "server graph instantiate");
-  graphs[prec][tier] = ex;
+  graphs[prec][key] = ex;
   *out = ex;
   return AMY_OK;
 }
@@ -284,7 +285,7 @@ void amy_server::run() {
     }
     bool ok = true;
     for (int prec = 0; prec < 2 && ok; ++prec) {
-      int n = 0, lds = 0;
+      int n = 0, lds = 0, fs = 0;
       int32_t* meta = h_meta[prec];
       meta[1] = 0;
       for (Request* r : act) {
@@ -310,6 +311,7 @@ void amy_server::run() {
         B.tiles = (int32_t)((pl.dev.n_x + per_tile - 1) / per_tile);
         meta[n + 2] = meta[n + 1] + B.tiles;
         lds = std::max(lds, pl.dev.grp_g > 1 ? pl.dev.lds_bytes_group : pl.dev.lds_bytes_tail);
+        if (pl.mode != AMY_MODE_STORED) fs = std::max(fs, amy_batch_family_set(pl.dev.kind, pl.dev.n));
         ++n;
       }
       if (n == 0) continue;
@@ -321,7 +323,7 @@ void amy_server::run() {
           break;
         }
       hipGraphExec_t ex;
-      if (step_graph(prec, tier, &ex) != AMY_OK) {
+      if (step_graph(prec, fs, tier, &ex) != AMY_OK) {
         fail_active("server step graph", hipErrorUnknown);
         ok = false;
         break;

@@ -1,12 +1,15 @@
 // amy_batch.hip -- many systems of uneven sizes in one launch.
 //
+// k_batch_init / k_batch_tail: labels and terminal values, then the FP64
+// row-tail pass, over every system's 64-state tiles.
 // k_batch_persistent: one cooperative launch runs every Bellman step of
 // every system.  Systems are sorted by horizon (longest first), so the
 // systems still active at global step s form a prefix; the work items of a
-// phase are their 64-state tiles.  Workgroups (one wave each) take items
-// from atomic work queues -- one queue per XCD over a contiguous item range,
-// stealing from the other XCDs' queues when their own is empty -- and a
-// grid-wide barrier separates the phases (init, then step 0 .. maxT-1).
+// phase are their tiles (64 states, or 64 / G states for the group
+// variants).  Workgroups (one wave each) take items from atomic work queues
+// -- one queue per XCD over a contiguous item range, stealing from the
+// other XCDs' queues when their own is empty -- and a grid-wide barrier
+// separates the phases (step 0 .. maxT-1).
 // Every barrier wait is bounded: a wave that waits too long records an
 // error and carries on, so the grid always drains.
 //
@@ -50,24 +53,20 @@ template <int KIND, int N, int G, bool F64>
 __device__ __forceinline__ void run_otf_g(const BatchSys& B, uint32_t s, int t, unsigned char* smem) {
   const DevProblem& P = B.P;
   const int k = B.horizon - t;
-  const bool first = (t == 0) && B.want_tail, last = (k == 1);
+  const bool last = (k == 1);
   int16_t* pol = B.pol ? B.pol + (int64_t)(k - 1) * P.n_x : nullptr;
+  // the FP64 tail is a pass of its own (k_batch_tail / the server's start),
+  // so the steps carry no tail code and keep their register budget low
   if constexpr (F64) {
     const double* Vin = (const double*)((t & 1) ? B.V1 : B.V0);
     double* Vo = last ? B.Vout : (double*)((t & 1) ? B.V0 : B.V1);
-    if (first) call_variant<KIND, N, G, double, double, double, double, false, true>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
-    else call_variant<KIND, N, G, double, double, double, double, false, false>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
+    call_variant<KIND, N, G, double, double, double, double, false, false>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
   } else {
     const float* Vin = (const float*)((t & 1) ? B.V1 : B.V0);
-    if (last) {
-      double* Vo = B.Vout;
-      if (first) call_variant<KIND, N, G, float, double, float, double, false, true>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
-      else call_variant<KIND, N, G, float, double, float, double, false, false>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
-    } else {
-      float* Vo = (float*)((t & 1) ? B.V0 : B.V1);
-      if (first) call_variant<KIND, N, G, float, float, float, float, true, true>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
-      else call_variant<KIND, N, G, float, float, float, float, true, false>(P, s, Vin, Vo, B.label, pol, B.tailmax, smem);
-    }
+    if (last)
+      call_variant<KIND, N, G, float, double, float, double, false, false>(P, s, Vin, B.Vout, B.label, pol, B.tailmax, smem);
+    else
+      call_variant<KIND, N, G, float, float, float, float, true, false>(P, s, Vin, (float*)((t & 1) ? B.V0 : B.V1), B.label, pol, B.tailmax, smem);
   }
 }
 
@@ -144,6 +143,22 @@ int amy_batch_family_set(int kind, int n) {
   AMY_BATCH_FAMILIES_SMALL(X)
 #undef X
   return 1;
+}
+
+// FP64 row tails of one 64-state tile of system B, max into B.tailmax.
+template <int FS>
+__device__ __forceinline__ void tail_tile(const BatchSys& B, uint32_t tile) {
+  const uint32_t s = tile * BATCH_BLOCK + (threadIdx.x & 63);
+  double tmax = 0.0;
+#define X(K, N_) \
+  case K * 16 + N_: tmax = tail_state<K, N_>(B.P, s, B.label); break;
+  if constexpr (FS == 0) {
+    switch (B.P.kind * 16 + B.P.n) { AMY_BATCH_FAMILIES_SMALL(X) }
+  } else {
+    switch (B.P.kind * 16 + B.P.n) { AMY_BATCH_FAMILIES(X) }
+  }
+#undef X
+  wave_max_to(tmax, B.tailmax);
 }
 
 template <bool F64>
@@ -229,21 +244,18 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_persistent(const BatchSys
                                                                   int xcd_order) {
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned gen = 0;
-  for (int phase = 0; phase <= max_steps; ++phase) {
-    const int nact = (phase == 0) ? nsys : active[phase - 1];
+  for (int phase = 0; phase < max_steps; ++phase) {
+    const int nact = active[phase];
     const uint32_t nitems = (uint32_t)tprefix[nact];
     int q = 0;
     uint32_t first, last;
     while (grab(ctl, phase, nitems, chunk, xcd_order != 0, q, first, last)) {
       for (uint32_t it = first; it < last; ++it) {
         const int j = find_sys(tprefix, nact, it);
-        const BatchSys& B = sys[j];
-        const uint32_t tile = it - (uint32_t)tprefix[j];
-        if (phase == 0) init_tile<F64>(B, tile);
-        else run_tile<F64, FS, false>(B, tile, phase - 1, smem);
+        run_tile<F64, FS, false>(sys[j], it - (uint32_t)tprefix[j], phase, smem);
       }
     }
-    if (phase < max_steps) grid_barrier(ctl, gridDim.x, gen);
+    if (phase + 1 < max_steps) grid_barrier(ctl, gridDim.x, gen);
   }
 }
 
@@ -267,13 +279,26 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_step(const BatchSys* __re
   }
 }
 
+// Labels and terminal values of every system (64-state tiles, tp64 their
+// prefix sums).
 template <bool F64>
 __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_init(const BatchSys* __restrict__ sys, int nsys,
-                                                            const int32_t* __restrict__ tprefix) {
-  const uint32_t nitems = (uint32_t)tprefix[nsys];
+                                                            const int32_t* __restrict__ tp64) {
+  const uint32_t nitems = (uint32_t)tp64[nsys];
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const int j = find_sys(tprefix, nsys, it);
-    init_tile<F64>(sys[j], it - (uint32_t)tprefix[j]);
+    const int j = find_sys(tp64, nsys, it);
+    init_tile<F64>(sys[j], it - (uint32_t)tp64[j]);
+  }
+}
+
+// FP64 tail pass of the systems that want it (after k_batch_init).
+template <int FS>
+__global__ void __launch_bounds__(BATCH_BLOCK) k_batch_tail(const BatchSys* __restrict__ sys, int nsys,
+                                                            const int32_t* __restrict__ tp64) {
+  const uint32_t nitems = (uint32_t)tp64[nsys];
+  for (uint32_t it = xcd_block(blockIdx.x, gridDim.x); it < nitems; it += gridDim.x) {
+    const int j = find_sys(tp64, nsys, it);
+    if (sys[j].want_tail) tail_tile<FS>(sys[j], it - (uint32_t)tp64[j]);
   }
 }
 
@@ -320,6 +345,13 @@ hipError_t amy_launch_batch_init(bool f64, const BatchSys* sys, int nsys, const 
                                  hipStream_t st) {
   if (f64) hipLaunchKernelGGL((k_batch_init<true>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tprefix);
   else hipLaunchKernelGGL((k_batch_init<false>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tprefix);
+  return hipGetLastError();
+}
+
+hipError_t amy_launch_batch_tail(int fs, const BatchSys* sys, int nsys, const int32_t* tp64, unsigned grid,
+                                 hipStream_t st) {
+  if (fs == 0) hipLaunchKernelGGL((k_batch_tail<0>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tp64);
+  else hipLaunchKernelGGL((k_batch_tail<1>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tp64);
   return hipGetLastError();
 }
 

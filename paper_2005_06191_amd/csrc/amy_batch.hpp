@@ -17,6 +17,9 @@ const void* amy_batch_step_kernel(bool f64, int fs);
 // meta[0] = number of systems, meta[1..] = tile prefix sums (device memory)
 hipError_t amy_launch_batch_step(bool f64, int fs, unsigned grid, size_t lds, const BatchSys* sys,
                                  const int32_t* meta, hipStream_t st);
-hipError_t amy_launch_batch_init(bool f64, const BatchSys* sys, int nsys, const int32_t* tprefix, unsigned grid,
+// tp64: prefix sums of the systems' 64-state tiles
+hipError_t amy_launch_batch_init(bool f64, const BatchSys* sys, int nsys, const int32_t* tp64, unsigned grid,
+                                 hipStream_t st);
+hipError_t amy_launch_batch_tail(int fs, const BatchSys* sys, int nsys, const int32_t* tp64, unsigned grid,
                                  hipStream_t st);
 hipError_t amy_launch_fill_u32(unsigned* p, size_t n, hipStream_t st);

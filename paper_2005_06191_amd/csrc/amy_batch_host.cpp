@@ -56,10 +56,12 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
   std::stable_sort(bp.order.begin(), bp.order.end(),
                    [&](int a, int b) { return probs[a].horizon > probs[b].horizon; });
   bp.tprefix.assign(count + 1, 0);
+  bp.tp64.assign(count + 1, 0);
   for (int r = 0; r < count; ++r) {
     const DevProblem& D = bp.plans[bp.order[r]].dev;
     const int per_tile = 64 / std::max(1, (int)D.grp_g);  // states per 64-lane tile
     bp.tprefix[r + 1] = bp.tprefix[r] + (int32_t)((D.n_x + per_tile - 1) / per_tile);
+    bp.tp64[r + 1] = bp.tp64[r] + (int32_t)((D.n_x + 63) / 64);
   }
   bp.active.assign(std::max(bp.maxT, 1), 0);
   for (int s = 0; s < bp.maxT; ++s) {
@@ -70,6 +72,7 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
   uint64_t o = 0;
   bp.off_sys = o;  o = al256(o + (uint64_t)count * sizeof(BatchSys));
   bp.off_tp = o;   o = al256(o + (uint64_t)(count + 1) * 4);
+  bp.off_tp64 = o; o = al256(o + (uint64_t)(count + 1) * 4);
   bp.off_act = o;  o = al256(o + (uint64_t)bp.active.size() * 4);
   bp.off_ctl = o;  o = al256(o + sizeof(BatchCtl));
   bp.base.assign(count, 0);
@@ -122,6 +125,7 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
   hipError_t e;
   if ((e = hipMemcpyAsync(ws + bp.off_sys, sys.data(), sizeof(BatchSys) * count, hipMemcpyHostToDevice, hs)) ||
       (e = hipMemcpyAsync(ws + bp.off_tp, bp.tprefix.data(), 4 * bp.tprefix.size(), hipMemcpyHostToDevice, hs)) ||
+      (e = hipMemcpyAsync(ws + bp.off_tp64, bp.tp64.data(), 4 * bp.tp64.size(), hipMemcpyHostToDevice, hs)) ||
       (e = hipMemcpyAsync(ws + bp.off_act, bp.active.data(), 4 * bp.active.size(), hipMemcpyHostToDevice, hs)))
     return amy_hip_fail(e, "batch tables upload");
   if ((e = amy_launch_fill_u32((unsigned*)(ws + bp.off_ctl), sizeof(BatchCtl) / 4, hs)) != hipSuccess)
@@ -139,15 +143,21 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
     hipEventCreate(&ev[1]);
     hipEventRecord(ev[0], hs);
   }
-  e = amy_launch_batch_persistent(bp.f64, bp.fs, grid, bp.lds, (const BatchSys*)(ws + bp.off_sys), count,
-                                  (const int32_t*)(ws + bp.off_tp), (const int32_t*)(ws + bp.off_act), bp.maxT,
-                                  (BatchCtl*)(ws + bp.off_ctl), std::max(1, tune.chunk), tune.xcd_order, hs);
+  const BatchSys* dsys = (const BatchSys*)(ws + bp.off_sys);
+  const int32_t* dtp64 = (const int32_t*)(ws + bp.off_tp64);
+  const unsigned g64 = (unsigned)std::min<int64_t>(std::max<int64_t>(bp.tp64[count], 1), (int64_t)ncu * 16);
+  e = amy_launch_batch_init(bp.f64, dsys, count, dtp64, g64, hs);
+  if (e == hipSuccess && want_tail) e = amy_launch_batch_tail(bp.fs, dsys, count, dtp64, g64, hs);
+  if (e == hipSuccess && bp.maxT > 0)
+    e = amy_launch_batch_persistent(bp.f64, bp.fs, grid, bp.lds, dsys, count, (const int32_t*)(ws + bp.off_tp),
+                                    (const int32_t*)(ws + bp.off_act), bp.maxT, (BatchCtl*)(ws + bp.off_ctl),
+                                    std::max(1, tune.chunk), tune.xcd_order, hs);
   if (e != hipSuccess) {
     if (ms_out) {
       hipEventDestroy(ev[0]);
       hipEventDestroy(ev[1]);
     }
-    return amy_hip_fail(e, "batch cooperative launch");
+    return amy_hip_fail(e, "batch launch");
   }
   if (ms_out) {
     hipEventRecord(ev[1], hs);

@@ -89,12 +89,13 @@ __device__ __forceinline__ void wave_max_to(double tmax, unsigned long long* tai
     atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
 }
 
-// Stand-alone tail pass (used when no sweep runs, T_d = 0): max over rows
-// (x free, all u) of P_mu(grid box) - P_mu(kept window), FP64.
+// Stand-alone tail pass (when no sweep computes it: T_d = 0, and the
+// batched launches): max over rows (x free, all u) of
+// P_mu(grid box) - P_mu(kept window), FP64.
+// tail_state: the max over the inputs of state s's row tails (0 for states
+// off the free set and past the grid).
 template <int KIND, int N>
-__global__ void __launch_bounds__(LANE_BLOCK) k_tail(DevProblem P, const uint8_t* __restrict__ label,
-                                                     unsigned long long* __restrict__ tailmax) {
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
+__device__ __forceinline__ double tail_state(const DevProblem& P, uint32_t s, const uint8_t* __restrict__ label) {
   double tmax = 0.0;
   if (s < (uint32_t)P.n_x && label[s] == LBL_FREE) {
     double x[N];
@@ -120,7 +121,14 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_tail(DevProblem P, const uint8_t
       iw.next(P);
     }
   }
-  wave_max_to(tmax, tailmax);
+  return tmax;
+}
+
+template <int KIND, int N>
+__global__ void __launch_bounds__(LANE_BLOCK) k_tail(DevProblem P, const uint8_t* __restrict__ label,
+                                                     unsigned long long* __restrict__ tailmax) {
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
+  wave_max_to(tail_state<KIND, N>(P, s, label), tailmax);
 }
 
 // ------------------------------------------------------------- OTF sweep

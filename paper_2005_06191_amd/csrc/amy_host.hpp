@@ -45,13 +45,14 @@ hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_
 struct BatchPlan {
   std::vector<Plan> plans;        // input order
   std::vector<int> order;         // launch order (horizon descending) -> input index
-  std::vector<int32_t> tprefix;   // tile prefix sums in launch order
+  std::vector<int32_t> tprefix;   // tile prefix sums in launch order (tiles of the sweep variant)
+  std::vector<int32_t> tp64;      // 64-state tile prefix sums in launch order (init, tail)
   std::vector<int32_t> active;    // systems still running at each global step
   bool f64 = false;
   int maxT = 0;
   int fs = 0;                     // family set compiled into the launch (0: 2-D / 3-D, 1: all)
   size_t lds = 0;                 // dynamic LDS of the launch
-  uint64_t off_sys = 0, off_tp = 0, off_act = 0, off_ctl = 0, ws_bytes = 0;
+  uint64_t off_sys = 0, off_tp = 0, off_tp64 = 0, off_act = 0, off_ctl = 0, ws_bytes = 0;
   std::vector<uint64_t> base;     // per system (input order): its region
 };
 

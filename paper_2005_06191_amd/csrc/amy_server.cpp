@@ -268,6 +268,10 @@ void amy_server::run() {
                                      r->prob.horizon == 0 ? vout : nullptr,
                                      (unsigned long long*)(b + pl.off_tail), stream);
       if (e == hipSuccess) e = amy_enqueue_prepare(pl, stream, b, r->prob.horizon);
+      // requests on the batched step get their FP64 tail from a pass of its own
+      if (e == hipSuccess && !r->solo && pl.mode != AMY_MODE_STORED && r->prob.horizon > 0)
+        e = amy_launch_tail(pl.dev, (const uint8_t*)(b + pl.off_label), (unsigned long long*)(b + pl.off_tail),
+                            stream);
       if (e == hipSuccess && pl.mode == AMY_MODE_STORED && r->prob.horizon > 0)
         e = amy_launch_build(pl.dev, pl.f64, (const uint8_t*)(b + pl.off_label), b + pl.off_T,
                              (int32_t*)(b + pl.off_org), (unsigned long long*)(b + pl.off_tail), stream);

@@ -308,7 +308,22 @@ __device__ __forceinline__ AT contract(const DevProblem& P, const MT* __restrict
   const int L = P.L[D];
   const MT* td = t + toff[D] * ts;
   AT acc = AT(0), c = AT(0);
-  for (int k = 0; k < L; ++k) {
+  int k0 = 0;
+  if constexpr (D == N - 1 && !(COMP && D == 0)) {
+    // innermost run: four gathers in flight, summed in slot order
+    for (; k0 + 4 <= L; k0 += 4) {
+      AT v[4];
+      MT m[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        v[j] = AT(V[base + k0 + j]);
+        m[j] = td[(k0 + j) * ts];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc = fma_(AT(m[j]), v[j], acc);
+    }
+  }
+  for (int k = k0; k < L; ++k) {
     AT inner;
     if constexpr (D == N - 1) inner = AT(V[base + k]);
     else inner = contract<D + 1, N, MT, AT, VT, COMP>(P, t, ts, toff, V, base + (int64_t)k * P.stride[D]);

@@ -30,7 +30,19 @@ __device__ __forceinline__ AT gsum(const DevProblem& P, int nout, const MT* __re
     if (D < nout) {
       const MT* td = t + P.goff[D];
       AT acc = AT(0);
-      for (int k = 0; k < P.L[D]; ++k)
+      int k = 0;
+      if constexpr (D >= N - 2) {
+        // the last levels: four sub-sums (gathers) in flight, added in slot order
+        for (; k + 4 <= P.L[D]; k += 4) {
+          AT in[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            in[j] = gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, off + (int64_t)(k + j) * P.stride[D]);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc = fma_(AT(td[k + j]), in[j], acc);
+        }
+      }
+      for (; k < P.L[D]; ++k)
         acc = fma_(AT(td[k]), gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, off + (int64_t)k * P.stride[D]), acc);
       return acc;
     }

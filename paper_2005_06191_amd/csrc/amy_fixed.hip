@@ -149,28 +149,35 @@ __device__ __forceinline__ void dim_step(const DevProblem& P, const InputWalk& i
 // Levels below SH::BL are unrolled (their gathers issue together); the
 // levels above are loops, one gather block per iteration, which bounds the
 // registers a row needs.
-template <int D, class SH, class MT, class AT, class VT, bool COMP>
+template <int D, class SH, class MT, class AT, class VT, bool COMP, bool LL = false>
 __device__ __forceinline__ AT contract_fixed(const DevProblem& P, const FixedRow<SH, MT>& R,
-                                             const VBuf<VT>& vb, uint32_t voff, uint32_t soff);
+                                             const VBuf<VT>& vb, uint32_t voff, uint32_t soff,
+                                             const MT* ll = nullptr);
 
-template <int D, class SH, class MT, class AT, class VT, bool COMP>
+// LL: the loop levels' masses are also in the lane's LDS slot ll
+// ([level * LMAX + k][lane]) and are read from there by index.
+template <int D, class SH, class MT, class AT, class VT, bool COMP, bool LL = false>
 __device__ __forceinline__ void contract_step(const DevProblem& P, const FixedRow<SH, MT>& R,
                                               const VBuf<VT>& vb, uint32_t voff, uint32_t soff, int k,
-                                              AT& acc, AT& c) {
+                                              AT& acc, AT& c, const MT* ll) {
   AT inner;
   if constexpr (D == SH::N - 1) {
     inner = AT(vb.load(voff + (uint32_t)(k * sizeof(VT)), soff));
   } else {
-    inner = contract_fixed<D + 1, SH, MT, AT, VT, COMP>(
-        P, R, vb, voff, soff + (uint32_t)k * (uint32_t)P.stride[D] * (uint32_t)sizeof(VT));
+    inner = contract_fixed<D + 1, SH, MT, AT, VT, COMP, LL>(
+        P, R, vb, voff, soff + (uint32_t)k * (uint32_t)P.stride[D] * (uint32_t)sizeof(VT), ll);
   }
   // mass of slot k; in a loop level k is a uniform register, so pick it
-  // with selects rather than an indexed (scratch) access
+  // with selects (or from LDS) rather than an indexed register access
   MT mk;
   if constexpr (D < SH::BL) {
-    mk = R.m[D][0];
+    if constexpr (LL) {
+      mk = ll[(D * SH::LMAX + k) * FIX_BLOCK];
+    } else {
+      mk = R.m[D][0];
 #pragma unroll
-    for (int j = 1; j < SH::L[D]; ++j) mk = (k == j) ? R.m[D][j] : mk;
+      for (int j = 1; j < SH::L[D]; ++j) mk = (k == j) ? R.m[D][j] : mk;
+    }
   } else {
     mk = R.m[D][k];
   }
@@ -184,17 +191,17 @@ __device__ __forceinline__ void contract_step(const DevProblem& P, const FixedRo
   }
 }
 
-template <int D, class SH, class MT, class AT, class VT, bool COMP>
+template <int D, class SH, class MT, class AT, class VT, bool COMP, bool LL>
 __device__ __forceinline__ AT contract_fixed(const DevProblem& P, const FixedRow<SH, MT>& R,
-                                             const VBuf<VT>& vb, uint32_t voff, uint32_t soff) {
+                                             const VBuf<VT>& vb, uint32_t voff, uint32_t soff, const MT* ll) {
   constexpr int L = SH::L[D];
   AT acc = AT(0), c = AT(0);
   if constexpr (D < SH::BL) {
 #pragma clang loop unroll(disable)
-    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VT, COMP>(P, R, vb, voff, soff, k, acc, c);
+    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VT, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);
   } else {
 #pragma unroll
-    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VT, COMP>(P, R, vb, voff, soff, k, acc, c);
+    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VT, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);
   }
   return acc;
 }
@@ -504,7 +511,7 @@ struct RelDrift<AMY_DYN_UNICYCLE_, 3> {
   }
 };
 
-#define REL_SLOTS 8  // relative table entry: up to 8 masses
+#define REL_SLOTS AMY_TABLE_SLOTS  // masses per table entry
 
 template <int KIND, int N, class MT>
 __global__ void __launch_bounds__(64) k_rel_build(DevProblem P, MT* __restrict__ rm, int32_t* __restrict__ rlo) {
@@ -686,6 +693,140 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_rel(DevProblem P, const VI*
   if (pol) pol[s] = (int16_t)arg;
 }
 
+// ---------------------------------------------------------- memoised tables
+//
+// A dimension whose mean reads few state coordinates (the room ring: its
+// room and the two neighbours; the 7-D vehicle: at most four) has few
+// distinct 1-D tables over the whole grid: one per (context cells, input
+// digits).  k_memo_build runs the per-state code (mean, window, masses) once
+// per such entry, with the context coordinates at their cell centres, so an
+// entry holds exactly the bits a state with that context computes;
+// k_sweep_memo (the steps without the FP64 tail) loads a row's tables
+// instead of computing them.
+template <int KIND, int N, class MT>
+__global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict__ rm, int32_t* __restrict__ ro) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  if (e >= P.rel_entries) return;
+  int i = 0;
+#pragma unroll
+  for (int d = 1; d < N; ++d)
+    if (e >= P.rel_off[d]) i = d;
+  const int idx = e - P.rel_off[i];
+  const int c = idx % P.rcount[i];
+  int cx = idx / P.rcount[i];
+  double x[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) x[d] = P.lo[d] + 0.5 * P.h[d];
+  for (int k = P.mctx_n[i] - 1; k >= 0; --k) {
+    const int d = P.mctx[i][k];
+    const int j = cx % P.count[d];
+    cx /= P.count[d];
+#pragma unroll
+    for (int dd = 0; dd < N; ++dd)
+      if (dd == d) x[dd] = P.lo[dd] + ((double)j + 0.5) * P.h[dd];
+  }
+  InputWalk iw;
+#pragma unroll
+  for (int k = 0; k < AMY_MAXI; ++k) {
+    const int mlt = P.rmult[i][k];
+    iw.dig[k] = (k < P.m && mlt > 0) ? (c / mlt) % P.ucount[k] : 0;
+  }
+  double u[AMY_MAXI], mu[N];
+  iw.values(P, u);
+  typename Dyn<KIND, N>::State st;
+  Dyn<KIND, N>::prep(P, x, st);
+  Dyn<KIND, N>::apply(P, st, x, u, mu);
+  double m_i = mu[0];
+#pragma unroll
+  for (int dd = 1; dd < N; ++dd)
+    if (dd == i) m_i = mu[dd];
+  MT* t = rm + (int64_t)e * REL_SLOTS;
+  const Win w = dim_table<MT>(P, i, m_i, t, 1);
+  for (int k = P.L[i]; k < REL_SLOTS; ++k) t[k] = MT(0);
+  ro[e] = w.o;
+}
+
+// Loads of every dimension's entry for the current input, then origins.
+template <int I, class SH, class MT>
+__device__ __forceinline__ void memo_load(const DevProblem& P, const InputWalk& iw, const int* cx,
+                                          const MT* __restrict__ rm, const int32_t* __restrict__ ro,
+                                          FixedRow<SH, MT>& R, uint32_t& base) {
+  if constexpr (I < SH::N) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < AMY_MAXI; ++k) c += iw.dig[k] * P.rmult[I][k];
+    const int e = P.rel_off[I] + cx[I] * P.rcount[I] + c;
+    const MT* tp = rm + (int64_t)e * REL_SLOTS;
+#pragma unroll
+    for (int k = 0; k < SH::L[I]; ++k) R.m[I][k] = tp[k];
+    base += (uint32_t)ro[e] * (uint32_t)P.stride[I];
+    memo_load<I + 1, SH, MT>(P, iw, cx, rm, ro, R, base);
+  }
+}
+
+template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP>
+__global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI* __restrict__ Vin,
+                                                          VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                                          int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                          const int32_t* __restrict__ ro) {
+  constexpr int N = SH::N;
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * FIX_BLOCK + threadIdx.x;
+  if (s >= (uint32_t)P.n_x) return;
+  const uint8_t lb = label[s];
+  if (lb != LBL_FREE) {
+    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
+    if (pol) pol[s] = -1;
+    return;
+  }
+  int j[N];
+  {
+    uint32_t r = s;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      j[i] = (int)(r % (uint32_t)P.count[i]);
+      r /= (uint32_t)P.count[i];
+    }
+  }
+  int cx[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    int v = 0;
+    for (int k = 0; k < P.mctx_n[i]; ++k) {
+      int jk = j[0];
+#pragma unroll
+      for (int d = 1; d < N; ++d)
+        if (d == P.mctx[i][k]) jk = j[d];
+      v += jk * P.mmult[i][k];
+    }
+    cx[i] = v;
+  }
+  const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
+  extern __shared__ __align__(16) unsigned char smem[];
+  MT* ll = reinterpret_cast<MT*>(smem) + threadIdx.x;  // loop levels' masses
+  FixedRow<SH, MT> R;
+  InputWalk iw;
+  iw.reset();
+  AT best = AT(-1);
+  int arg = 0;
+  for (int u = 0; u < P.n_u; ++u) {
+    uint32_t base = 0;
+    memo_load<0, SH, MT>(P, iw, cx, rm, ro, R, base);
+#pragma unroll
+    for (int d = 0; d < SH::BL; ++d)
+#pragma unroll
+      for (int k = 0; k < SH::LMAX; ++k)
+        if (k < SH::L[d]) ll[(d * SH::LMAX + k) * FIX_BLOCK] = R.m[d][k];
+    const AT q = contract_fixed<0, SH, MT, AT, VI, COMP, true>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
+    if (q > best) {
+      best = q;
+      arg = u;
+    }
+    iw.next(P);
+  }
+  Vout[s] = VO(best);
+  if (pol) pol[s] = (int16_t)arg;
+}
+
 // ------------------------------------------------------------- launchers
 
 template <int KIND, class SH>
@@ -698,8 +839,19 @@ struct FixedLaunch {
   }
   template <class MT, class AT, class VI, class VO, bool COMP>
   static void go(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
-                 unsigned long long* tailmax, hipStream_t st) {
+                 unsigned long long* tailmax, const void* tables, hipStream_t st) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
+    if constexpr (SH::LMAX <= REL_SLOTS) {
+      if (!tailmax && tables && P.tables == 2) {
+      const MT* rm = (const MT*)tables;
+      const int32_t* ro = (const int32_t*)((const char*)tables +
+                                           (((uint64_t)P.rel_entries * REL_SLOTS * sizeof(MT) + 255) & ~255ull));
+      const size_t lds = (size_t)(SH::BL > 0 ? SH::BL : 1) * SH::LMAX * sizeof(MT) * FIX_BLOCK;
+      hipLaunchKernelGGL((k_sweep_memo<KIND, SH, MT, AT, VI, VO, COMP>), g, b, lds, st, P, (const VI*)Vin, (VO*)Vout,
+                         label, pol, rm, ro);
+      return;
+      }
+    }
     if (tailmax)
       hipLaunchKernelGGL((k_sweep_fixed<KIND, SH, MT, AT, VI, VO, COMP, true>), g, b, P.lds_bytes_tail, st, P,
                          (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
@@ -708,12 +860,23 @@ struct FixedLaunch {
                          (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
   }
   static hipError_t sweep(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout, const uint8_t* label,
-                          int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
+                          int16_t* pol, unsigned long long* tailmax, const void* tables, hipStream_t st) {
     switch (sk) {
-      case SWEEP_F64: go<double, double, double, double, false>(P, Vin, Vout, label, pol, tailmax, st); break;
-      case SWEEP_F32: go<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, st); break;
-      case SWEEP_F32_LAST: go<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, st); break;
+      case SWEEP_F64: go<double, double, double, double, false>(P, Vin, Vout, label, pol, tailmax, tables, st); break;
+      case SWEEP_F32: go<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, tables, st); break;
+      case SWEEP_F32_LAST:
+        go<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, tables, st);
+        break;
     }
+    return hipGetLastError();
+  }
+  static hipError_t memo_build(const DevProblem& P, bool f64, void* tables, hipStream_t st) {
+    if (SH::LMAX > REL_SLOTS) return hipErrorInvalidValue;  // the host never plans it
+    const dim3 g((unsigned)((P.rel_entries + 63) / 64)), b(64);
+    const uint64_t msz = f64 ? 8 : 4;
+    int32_t* ro = (int32_t*)((char*)tables + (((uint64_t)P.rel_entries * REL_SLOTS * msz + 255) & ~255ull));
+    if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double>), g, b, 0, st, P, (double*)tables, ro);
+    else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float>), g, b, 0, st, P, (float*)tables, ro);
     return hipGetLastError();
   }
 };
@@ -879,9 +1042,18 @@ bool amy_fixed_available(const DevProblem& P) {
 
 hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
                                   const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
-                                  hipStream_t st) {
+                                  const void* tables, hipStream_t st) {
+#define X(K, SH)                          \
+  if (FixedLaunch<K, SH>::matches(P)) \
+    return FixedLaunch<K, SH>::sweep(P, sk, Vin, Vout, label, pol, tailmax, tables, st);
+  AMY_FIXED_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t amy_launch_memo_build(const DevProblem& P, bool f64, void* tables, hipStream_t st) {
 #define X(K, SH) \
-  if (FixedLaunch<K, SH>::matches(P)) return FixedLaunch<K, SH>::sweep(P, sk, Vin, Vout, label, pol, tailmax, st);
+  if (FixedLaunch<K, SH>::matches(P)) return FixedLaunch<K, SH>::memo_build(P, f64, tables, st);
   AMY_FIXED_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

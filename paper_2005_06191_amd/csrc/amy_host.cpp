@@ -134,6 +134,65 @@ static uint32_t dep_mask(const amy_problem* p, int i) {
 
 static const int LDS_BUDGET = 64 * 1024;  // bytes of dynamic LDS per 64-lane block
 
+// State coordinates the mean of dimension i reads (besides the inputs), as
+// the dynamics families are written; 0 when more than 4 or not known.
+static int memo_ctx(const amy_problem* p, int i, int* ctx) {
+  const int n = p->grid.n;
+  int c = 0;
+  auto add = [&](int d) {
+    for (int k = 0; k < c; ++k)
+      if (ctx[k] == d) return;
+    if (c < 4) ctx[c] = d;
+    ++c;
+  };
+  switch (p->dyn.kind) {
+    case AMY_DYN_AFFINE:
+      for (int j = 0; j < n; ++j)
+        if (p->dyn.params[i * n + j] != 0.0) add(j);
+      break;
+    case AMY_DYN_UNICYCLE: add(i); if (i < 2) add(2); break;
+    case AMY_DYN_ROOM: add((i + n - 1) % n); add(i); add((i + 1) % n); break;
+    case AMY_DYN_VEHICLE7: {
+      // x, y: speed, heading, slip angle; steering, speed: themselves;
+      // heading, yaw rate, slip angle: steering, speed, yaw rate, slip angle
+      static const int d[7][4] = {{0, 3, 4, 6}, {1, 3, 4, 6}, {2, -1, -1, -1}, {3, -1, -1, -1},
+                                  {2, 3, 4, 5}, {2, 3, 5, 6}, {2, 3, 5, 6}};
+      for (int k = 0; k < 4; ++k)
+        if (d[i][k] >= 0) add(d[i][k]);
+      break;
+    }
+    default: return 0;
+  }
+  if (c == 0) add(i);
+  return c <= 4 ? c : 0;
+}
+
+static const int64_t MEMO_BUDGET = 1 << 21;  // entries of memoised tables per solve
+
+// Memoised tables of a compiled-shape plan: false if some dimension's
+// context is unknown or the entries exceed the budget.
+static bool plan_memo(const amy_problem* p, DevProblem& D) {
+  int64_t off = 0;
+  for (int i = 0; i < D.n; ++i) {
+    if (D.L[i] > AMY_TABLE_SLOTS) return false;  // an entry holds at most that many masses
+    int ctx[4];
+    const int c = memo_ctx(p, i, ctx);
+    if (c <= 0) return false;
+    int64_t cells = 1;
+    for (int k = c - 1; k >= 0; --k) {
+      D.mmult[i][k] = (int32_t)cells;
+      cells *= D.count[ctx[k]];
+    }
+    D.mctx_n[i] = c;
+    for (int k = 0; k < 4; ++k) D.mctx[i][k] = k < c ? ctx[k] : 0;
+    D.rel_off[i] = (int32_t)off;
+    off += cells * D.rcount[i];
+    if (off > MEMO_BUDGET) return false;
+  }
+  D.rel_entries = (int32_t)off;
+  return true;
+}
+
 // Which dimensions get all their tables built once per state (the others
 // are rebuilt in the input loop when their mean changes), and the LDS layout.
 static amy_status plan_tables(const amy_problem* p, Plan* pl) {
@@ -413,7 +472,9 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   }
   pl->dev.variant = v;
   pl->dev.rel_entries = 0;
-  if (v == AMY_VARIANT_FACTORED && amy_rel_plan(pl->dev) > 0) {
+  pl->dev.tables = 0;
+  if ((v == AMY_VARIANT_FACTORED && amy_rel_plan(pl->dev) > 0 && (pl->dev.tables = 1)) ||
+      (v == AMY_VARIANT_FIXED && mode == AMY_MODE_OTF && plan_memo(p, pl->dev) && (pl->dev.tables = 2))) {
     // relative tables after the rest of the workspace: masses, then origins
     const uint64_t msz = pl->f64 ? 8 : 4, ne = (uint64_t)pl->dev.rel_entries;
     pl->off_rel = pl->ws_bytes;
@@ -479,7 +540,9 @@ hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_
   if (D.variant == AMY_VARIANT_FACTORED)
     return amy_launch_sweep_fac(D, sk, Vb[cur], out, label, pk, tail, D.rel_entries > 0 ? base + pl.off_rel : nullptr,
                                 st);
-  if (D.variant == AMY_VARIANT_FIXED) return amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk, tail, st);
+  if (D.variant == AMY_VARIANT_FIXED)
+    return amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk, tail, D.rel_entries > 0 ? base + pl.off_rel : nullptr,
+                                  st);
   if (D.grp_g > 1) return amy_launch_sweep_group(D, sk, Vb[cur], out, label, pk, tail, st);
   return amy_launch_sweep_otf(D, sk, Vb[cur], out, label, pk, tail, st);
 }
@@ -488,6 +551,7 @@ hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_
 // relative tables), after the labels and before the first step.
 hipError_t amy_enqueue_prepare(const Plan& pl, hipStream_t st, void* ws, int horizon) {
   if (pl.dev.rel_entries <= 0 || horizon < 1) return hipSuccess;
+  if (pl.dev.tables == 2) return amy_launch_memo_build(pl.dev, pl.f64, (char*)ws + pl.off_rel, st);
   return amy_launch_rel_build(pl.dev, pl.f64, (char*)ws + pl.off_rel, st);
 }
 

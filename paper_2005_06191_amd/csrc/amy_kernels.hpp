@@ -34,9 +34,12 @@ hipError_t amy_launch_sweep_stored(const DevProblem& P, SweepKind sk, const void
 // Fixed-window-shape sweep (amy_fixed.hip): available for the instantiated
 // window shapes only.
 bool amy_fixed_available(const DevProblem& P);
+// tables: the memoised tables (P.tables == 2) for the steps without the
+// FP64 tail, or nullptr.
 hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
                                   const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
-                                  hipStream_t st);
+                                  const void* tables, hipStream_t st);
+hipError_t amy_launch_memo_build(const DevProblem& P, bool f64, void* tables, hipStream_t st);
 // Factored compiled-shape sweep (inputs sharing the outer dimensions' windows).
 // rel: the shared relative tables (when P.rel_entries > 0) for the steps
 // without the FP64 tail; the tail step builds its tables per state.

@@ -10,6 +10,7 @@
 #define AMY_MAXD 8
 #define AMY_MAXI 4
 #define AMY_MAXP 128
+#define AMY_TABLE_SLOTS 8  // masses per entry of the shared / memoised 1-D tables
 
 enum { LBL_FREE = 0, LBL_ZERO = 1, LBL_ONE = 2 };
 
@@ -41,7 +42,15 @@ struct DevProblem {
   // (zero past the kept count) and their first cell's relative index.
   int32_t rctx[AMY_MAXD];
   int32_t rel_off[AMY_MAXD];
-  int32_t rel_entries;        // 0: no relative tables
+  int32_t rel_entries;        // 0: no shared tables
+  // Memoised tables (compiled-shape sweep): dimension i's mean depends only
+  // on the inputs and on the state's coordinates in dimensions mctx[i][0 ..
+  // mctx_n[i]); entry rel_off[i] + cx * rcount[i] + c holds the absolute
+  // window origin and masses for context cells cx = sum_k j_k mmult[i][k].
+  int32_t mctx_n[AMY_MAXD];
+  int32_t mctx[AMY_MAXD][4];
+  int32_t mmult[AMY_MAXD][4];
+  int32_t tables;             // 0 none, 1 relative (factored sweep), 2 memoised (compiled-shape sweep)
   int32_t toff[AMY_MAXD];     // first LDS table entry of dimension i
   int32_t ooff[AMY_MAXD];     // first cached-origin slot of dimension i
   int32_t lds_int_off;        // byte offset of the origin slots in a block's LDS

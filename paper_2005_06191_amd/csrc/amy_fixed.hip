@@ -764,28 +764,57 @@ __device__ __forceinline__ void memo_load(const DevProblem& P, const InputWalk& 
   }
 }
 
-template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP>
-__global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI* __restrict__ Vin,
-                                                          VO* __restrict__ Vout, const uint8_t* __restrict__ label,
-                                                          int16_t* __restrict__ pol, const MT* __restrict__ rm,
-                                                          const int32_t* __restrict__ ro) {
-  constexpr int N = SH::N;
-  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * FIX_BLOCK + threadIdx.x;
-  if (s >= (uint32_t)P.n_x) return;
-  const uint8_t lb = label[s];
-  if (lb != LBL_FREE) {
-    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
-    if (pol) pol[s] = -1;
-    return;
-  }
-  int j[N];
-  {
+// State of lane `lane` of workgroup b.  With at least three dimensions whose
+// three innermost counts are multiples of 4, and more than 8 cells in the
+// innermost one, a workgroup takes a 4 x 4 x 4 tile of those dimensions
+// (their windows overlap, so the gathers share cache lines); otherwise 64
+// consecutive states (which already span a 2-D plane of the innermost
+// dimensions when those are short).  j[]: the state's cells.
+template <int N>
+__device__ __forceinline__ uint32_t tiled_state(const DevProblem& P, uint32_t b, int lane, int* j) {
+  bool tiled = N >= 3 && P.count[N - 1] > 8;
+#pragma unroll
+  for (int d = (N >= 3 ? N - 3 : 0); d < N; ++d) tiled = tiled && (P.count[d] & 3) == 0;
+  uint32_t s = 0;
+  if (tiled) {
+    uint32_t r = b;
+#pragma unroll
+    for (int d = N - 1; d >= 0; --d) {
+      const bool inner = d >= N - 3;
+      const uint32_t td = inner ? (uint32_t)P.count[d] / 4u : (uint32_t)P.count[d];
+      const uint32_t c = r % td;
+      r /= td;
+      const int part = d == N - 1 ? (lane & 3) : (d == N - 2 ? ((lane >> 2) & 3) : (lane >> 4));
+      j[d] = inner ? (int)(c * 4u) + part : (int)c;
+      s += (uint32_t)j[d] * (uint32_t)P.stride[d];
+    }
+    if (r != 0) s = 0xffffffffu;  // past the last tile
+  } else {
+    s = b * FIX_BLOCK + (uint32_t)lane;
     uint32_t r = s;
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
       j[i] = (int)(r % (uint32_t)P.count[i]);
       r /= (uint32_t)P.count[i];
     }
+  }
+  return s;
+}
+
+template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP>
+__global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI* __restrict__ Vin,
+                                                          VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                                          int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                          const int32_t* __restrict__ ro) {
+  constexpr int N = SH::N;
+  int j[N];
+  const uint32_t s = tiled_state<N>(P, xcd_block(blockIdx.x, gridDim.x), threadIdx.x, j);
+  if (s >= (uint32_t)P.n_x) return;
+  const uint8_t lb = label[s];
+  if (lb != LBL_FREE) {
+    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
+    if (pol) pol[s] = -1;
+    return;
   }
   int cx[N];
 #pragma unroll

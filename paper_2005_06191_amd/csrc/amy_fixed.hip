@@ -703,8 +703,21 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_rel(DevProblem P, const VI*
 // entry holds exactly the bits a state with that context computes;
 // k_sweep_memo (the steps without the FP64 tail) loads a row's tables
 // instead of computing them.
-template <int KIND, int N, class MT>
-__global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict__ rm, int32_t* __restrict__ ro) {
+template <class MT>
+__device__ __forceinline__ MT origin_bits(int o) {
+  if constexpr (sizeof(MT) == 8) return __builtin_bit_cast(MT, (int64_t)o);
+  else return __builtin_bit_cast(MT, (int32_t)o);
+}
+template <class MT>
+__device__ __forceinline__ int origin_of(MT v) {
+  if constexpr (sizeof(MT) == 8) return (int)__builtin_bit_cast(int64_t, v);
+  else return (int)__builtin_bit_cast(int32_t, v);
+}
+
+// Entry e is the record rm[e*REC .. e*REC+REC): the masses of its window, zeros,
+// and the window origin's bits in the last slot.
+template <int KIND, int N, class MT, int REC>
+__global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict__ rm) {
   const int e = blockIdx.x * 64 + threadIdx.x;
   if (e >= P.rel_entries) return;
   int i = 0;
@@ -740,27 +753,35 @@ __global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict_
 #pragma unroll
   for (int dd = 1; dd < N; ++dd)
     if (dd == i) m_i = mu[dd];
-  MT* t = rm + (int64_t)e * REL_SLOTS;
+  MT t[REC];
   const Win w = dim_table<MT>(P, i, m_i, t, 1);
-  for (int k = P.L[i]; k < REL_SLOTS; ++k) t[k] = MT(0);
-  ro[e] = w.o;
+  for (int k = P.L[i]; k < REC - 1; ++k) t[k] = MT(0);
+  t[REC - 1] = origin_bits<MT>(w.o);
+  MT* dst = rm + (int64_t)e * REC;
+#pragma unroll
+  for (int k = 0; k < REC; ++k) dst[k] = t[k];
 }
 
-// Loads of every dimension's entry for the current input, then origins.
+template <class MT, int REC>
+struct alignas(REC * sizeof(MT)) MemoRec {
+  MT v[REC];
+};
+
+// Every dimension's record for the current input: masses and origin.
 template <int I, class SH, class MT>
 __device__ __forceinline__ void memo_load(const DevProblem& P, const InputWalk& iw, const int* cx,
-                                          const MT* __restrict__ rm, const int32_t* __restrict__ ro,
-                                          FixedRow<SH, MT>& R, uint32_t& base) {
+                                          const MT* __restrict__ rm, FixedRow<SH, MT>& R, uint32_t& base) {
   if constexpr (I < SH::N) {
+    constexpr int REC = amy_memo_rec(SH::LMAX);
     int c = 0;
 #pragma unroll
     for (int k = 0; k < AMY_MAXI; ++k) c += iw.dig[k] * P.rmult[I][k];
     const int e = P.rel_off[I] + cx[I] * P.rcount[I] + c;
-    const MT* tp = rm + (int64_t)e * REL_SLOTS;
+    const MemoRec<MT, REC> r = *reinterpret_cast<const MemoRec<MT, REC>*>(rm + (int64_t)e * REC);
 #pragma unroll
-    for (int k = 0; k < SH::L[I]; ++k) R.m[I][k] = tp[k];
-    base += (uint32_t)ro[e] * (uint32_t)P.stride[I];
-    memo_load<I + 1, SH, MT>(P, iw, cx, rm, ro, R, base);
+    for (int k = 0; k < SH::L[I]; ++k) R.m[I][k] = r.v[k];
+    base += (uint32_t)origin_of<MT>(r.v[REC - 1]) * (uint32_t)P.stride[I];
+    memo_load<I + 1, SH, MT>(P, iw, cx, rm, R, base);
   }
 }
 
@@ -804,8 +825,7 @@ __device__ __forceinline__ uint32_t tiled_state(const DevProblem& P, uint32_t b,
 template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP>
 __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI* __restrict__ Vin,
                                                           VO* __restrict__ Vout, const uint8_t* __restrict__ label,
-                                                          int16_t* __restrict__ pol, const MT* __restrict__ rm,
-                                                          const int32_t* __restrict__ ro) {
+                                                          int16_t* __restrict__ pol, const MT* __restrict__ rm) {
   constexpr int N = SH::N;
   int j[N];
   const uint32_t s = tiled_state<N>(P, xcd_block(blockIdx.x, gridDim.x), threadIdx.x, j);
@@ -839,7 +859,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI
   int arg = 0;
   for (int u = 0; u < P.n_u; ++u) {
     uint32_t base = 0;
-    memo_load<0, SH, MT>(P, iw, cx, rm, ro, R, base);
+    memo_load<0, SH, MT>(P, iw, cx, rm, R, base);
 #pragma unroll
     for (int d = 0; d < SH::BL; ++d)
 #pragma unroll
@@ -873,11 +893,9 @@ struct FixedLaunch {
     if constexpr (SH::LMAX <= REL_SLOTS) {
       if (!tailmax && tables && P.tables == 2) {
       const MT* rm = (const MT*)tables;
-      const int32_t* ro = (const int32_t*)((const char*)tables +
-                                           (((uint64_t)P.rel_entries * REL_SLOTS * sizeof(MT) + 255) & ~255ull));
       const size_t lds = (size_t)(SH::BL > 0 ? SH::BL : 1) * SH::LMAX * sizeof(MT) * FIX_BLOCK;
       hipLaunchKernelGGL((k_sweep_memo<KIND, SH, MT, AT, VI, VO, COMP>), g, b, lds, st, P, (const VI*)Vin, (VO*)Vout,
-                         label, pol, rm, ro);
+                         label, pol, rm);
       return;
       }
     }
@@ -902,10 +920,9 @@ struct FixedLaunch {
   static hipError_t memo_build(const DevProblem& P, bool f64, void* tables, hipStream_t st) {
     if (SH::LMAX > REL_SLOTS) return hipErrorInvalidValue;  // the host never plans it
     const dim3 g((unsigned)((P.rel_entries + 63) / 64)), b(64);
-    const uint64_t msz = f64 ? 8 : 4;
-    int32_t* ro = (int32_t*)((char*)tables + (((uint64_t)P.rel_entries * REL_SLOTS * msz + 255) & ~255ull));
-    if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double>), g, b, 0, st, P, (double*)tables, ro);
-    else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float>), g, b, 0, st, P, (float*)tables, ro);
+    constexpr int REC = amy_memo_rec(SH::LMAX);
+    if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double, REC>), g, b, 0, st, P, (double*)tables);
+    else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float, REC>), g, b, 0, st, P, (float*)tables);
     return hipGetLastError();
   }
 };

@@ -475,10 +475,17 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   pl->dev.tables = 0;
   if ((v == AMY_VARIANT_FACTORED && amy_rel_plan(pl->dev) > 0 && (pl->dev.tables = 1)) ||
       (v == AMY_VARIANT_FIXED && mode == AMY_MODE_OTF && plan_memo(p, pl->dev) && (pl->dev.tables = 2))) {
-    // relative tables after the rest of the workspace: masses, then origins
+    // tables after the rest of the workspace: shared relative tables hold
+    // masses then origins; memoised tables hold one record per entry
     const uint64_t msz = pl->f64 ? 8 : 4, ne = (uint64_t)pl->dev.rel_entries;
     pl->off_rel = pl->ws_bytes;
-    pl->ws_bytes += ((ne * 8 * msz + 255) & ~255ull) + ((ne * 4 + 255) & ~255ull);
+    if (pl->dev.tables == 2) {
+      int lmax = 1;
+      for (int i = 0; i < pl->dev.n; ++i) lmax = pl->dev.L[i] > lmax ? pl->dev.L[i] : lmax;
+      pl->ws_bytes += (ne * (uint64_t)amy_memo_rec(lmax) * msz + 255) & ~255ull;
+    } else {
+      pl->ws_bytes += ((ne * 8 * msz + 255) & ~255ull) + ((ne * 4 + 255) & ~255ull);
+    }
     if (budget && pl->ws_bytes > budget)
       return amy_fail(AMY_E_NOMEM, "workspace %llu B exceeds budget %llu B",
                       (unsigned long long)pl->ws_bytes, (unsigned long long)budget);

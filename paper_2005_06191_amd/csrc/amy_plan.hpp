@@ -12,6 +12,13 @@
 #define AMY_MAXP 128
 #define AMY_TABLE_SLOTS 8  // masses per entry of the shared / memoised 1-D tables
 
+// Slots of one memoised-table record: the window's masses, then the origin's
+// bits in the last slot, padded to a power of two so that a record is one
+// aligned vector load.
+static inline constexpr int amy_memo_rec(int lmax) {
+  return lmax + 1 <= 2 ? 2 : lmax + 1 <= 4 ? 4 : lmax + 1 <= 8 ? 8 : 16;
+}
+
 enum { LBL_FREE = 0, LBL_ZERO = 1, LBL_ONE = 2 };
 
 struct DevProblem {

@@ -50,10 +50,16 @@ struct ShapeT {
 // Raw buffer view of a V vector (offsets in bytes; out-of-range reads give 0).
 template <class VT>
 struct VBuf {
+  using value_type = VT;
   __amdgpu_buffer_rsrc_t r;
   __device__ __forceinline__ VBuf(const VT* p, uint32_t n)
       : r(__builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * (uint32_t)sizeof(VT)), 0x00020000)) {}
   __device__ __forceinline__ VT load(uint32_t voff, uint32_t soff) const;
+  // byte step of one cell along dimension D
+  template <int D>
+  __device__ __forceinline__ uint32_t step(const DevProblem& P) const {
+    return (uint32_t)P.stride[D] * (uint32_t)sizeof(VT);
+  }
 };
 template <>
 __device__ __forceinline__ float VBuf<float>::load(uint32_t voff, uint32_t soff) const {
@@ -149,30 +155,32 @@ __device__ __forceinline__ void dim_step(const DevProblem& P, const InputWalk& i
 // Levels below SH::BL are unrolled (their gathers issue together); the
 // levels above are loops, one gather block per iteration, which bounds the
 // registers a row needs.
-template <int D, class SH, class MT, class AT, class VT, bool COMP, bool LL = false>
+// VS is the source of V: VBuf (global memory, the grid's strides) or VLds
+// (a box of V staged in LDS, the box's strides).
+template <int D, class SH, class MT, class AT, class VS, bool COMP, int LL = 0>
 __device__ __forceinline__ AT contract_fixed(const DevProblem& P, const FixedRow<SH, MT>& R,
-                                             const VBuf<VT>& vb, uint32_t voff, uint32_t soff,
+                                             const VS& vb, uint32_t voff, uint32_t soff,
                                              const MT* ll = nullptr);
 
-// LL: the loop levels' masses are also in the lane's LDS slot ll
-// ([level * LMAX + k][lane]) and are read from there by index.
-template <int D, class SH, class MT, class AT, class VT, bool COMP, bool LL = false>
+// LL > 0: the loop levels' masses are also in the thread's LDS slot ll
+// ([level * LMAX + k][thread], LL threads) and are read from there by index.
+template <int D, class SH, class MT, class AT, class VS, bool COMP, int LL = 0>
 __device__ __forceinline__ void contract_step(const DevProblem& P, const FixedRow<SH, MT>& R,
-                                              const VBuf<VT>& vb, uint32_t voff, uint32_t soff, int k,
+                                              const VS& vb, uint32_t voff, uint32_t soff, int k,
                                               AT& acc, AT& c, const MT* ll) {
   AT inner;
   if constexpr (D == SH::N - 1) {
-    inner = AT(vb.load(voff + (uint32_t)(k * sizeof(VT)), soff));
+    inner = AT(vb.load(voff + (uint32_t)(k * sizeof(typename VS::value_type)), soff));
   } else {
-    inner = contract_fixed<D + 1, SH, MT, AT, VT, COMP, LL>(
-        P, R, vb, voff, soff + (uint32_t)k * (uint32_t)P.stride[D] * (uint32_t)sizeof(VT), ll);
+    inner = contract_fixed<D + 1, SH, MT, AT, VS, COMP, LL>(P, R, vb, voff,
+                                                            soff + (uint32_t)k * vb.template step<D>(P), ll);
   }
   // mass of slot k; in a loop level k is a uniform register, so pick it
   // with selects (or from LDS) rather than an indexed register access
   MT mk;
   if constexpr (D < SH::BL) {
-    if constexpr (LL) {
-      mk = ll[(D * SH::LMAX + k) * FIX_BLOCK];
+    if constexpr (LL > 0) {
+      mk = ll[(D * SH::LMAX + k) * LL];
     } else {
       mk = R.m[D][0];
 #pragma unroll
@@ -191,17 +199,17 @@ __device__ __forceinline__ void contract_step(const DevProblem& P, const FixedRo
   }
 }
 
-template <int D, class SH, class MT, class AT, class VT, bool COMP, bool LL>
+template <int D, class SH, class MT, class AT, class VS, bool COMP, int LL>
 __device__ __forceinline__ AT contract_fixed(const DevProblem& P, const FixedRow<SH, MT>& R,
-                                             const VBuf<VT>& vb, uint32_t voff, uint32_t soff, const MT* ll) {
+                                             const VS& vb, uint32_t voff, uint32_t soff, const MT* ll) {
   constexpr int L = SH::L[D];
   AT acc = AT(0), c = AT(0);
   if constexpr (D < SH::BL) {
 #pragma clang loop unroll(disable)
-    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VT, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);
+    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VS, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);
   } else {
 #pragma unroll
-    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VT, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);
+    for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VS, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);
   }
   return acc;
 }
@@ -247,7 +255,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fixed(DevProblem P, const V
         double win = 1.0, grid = 1.0;
         dim_step<0, SH, MT, TAIL>(P, iw, mu, S, R, base, win, grid);
         if constexpr (TAIL) tmax = fmax(tmax, grid - win);
-        const AT q = contract_fixed<0, SH, MT, AT, VI, COMP>(P, R, vb, base * (uint32_t)sizeof(VI), 0u);
+        const AT q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP>(P, R, vb, base * (uint32_t)sizeof(VI), 0u);
         if (q > best) {
           best = q;
           arg = u;
@@ -780,7 +788,8 @@ __device__ __forceinline__ void memo_load(const DevProblem& P, const InputWalk& 
     const MemoRec<MT, REC> r = *reinterpret_cast<const MemoRec<MT, REC>*>(rm + (int64_t)e * REC);
 #pragma unroll
     for (int k = 0; k < SH::L[I]; ++k) R.m[I][k] = r.v[k];
-    base += (uint32_t)origin_of<MT>(r.v[REC - 1]) * (uint32_t)P.stride[I];
+    R.o[I] = (uint32_t)origin_of<MT>(r.v[REC - 1]);
+    base += R.o[I] * (uint32_t)P.stride[I];
     memo_load<I + 1, SH, MT>(P, iw, cx, rm, R, base);
   }
 }
@@ -865,7 +874,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI
 #pragma unroll
       for (int k = 0; k < SH::LMAX; ++k)
         if (k < SH::L[d]) ll[(d * SH::LMAX + k) * FIX_BLOCK] = R.m[d][k];
-    const AT q = contract_fixed<0, SH, MT, AT, VI, COMP, true>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
+    const AT q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP, FIX_BLOCK>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
     if (q > best) {
       best = q;
       arg = u;
@@ -874,6 +883,177 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI
   }
   Vout[s] = VO(best);
   if (pol) pol[s] = (int16_t)arg;
+}
+
+// ------------------------------------------------------- staged V boxes
+//
+// A workgroup of 256 threads takes a 1 x 4 x 4 x 4 x 4 tile of a 5-D grid.
+// For each input the union of its threads' windows, which for the room ring
+// (every mean moves less than one cell per cell of its own coordinate and a
+// fraction of a cell per neighbour's cell) spans at most T + L - 1 cells in
+// a tiled dimension and L + 1 in the untiled one, is copied from V into LDS
+// once; the threads then read their windows from the box instead of
+// gathering them through the vector memory pipeline.  The box starts at the
+// window origin of the tile's first state, clamped to the grid; a thread
+// whose window does not fit in it gathers from V as the other sweeps do.
+// The contraction is the same code with the same order of operations, so
+// the result is bitwise that of k_sweep_memo.
+template <class SH>
+struct StageBox {
+  static_assert(SH::N == 5, "staged box: 5-D shapes");
+  static constexpr int C[5] = {SH::L[0] + 1, SH::L[1] + 3, SH::L[2] + 3, SH::L[3] + 3, SH::L[4] + 3};
+  static constexpr int S[5] = {C[1] * C[2] * C[3] * C[4], C[2] * C[3] * C[4], C[3] * C[4], C[4], 1};
+  static constexpr int SIZE = C[0] * S[0];
+  static constexpr int PLANE = S[1];        // cells of dims 2..4: one per staging thread
+  static constexpr int PLANES = C[0] * C[1];
+  static_assert(PLANE <= 256, "a plane of the box per workgroup pass");
+};
+
+template <int KIND, class SH>
+struct Staged {
+  static constexpr bool value = KIND == AMY_DYN_ROOM_ && SH::N == 5 && SH::LMAX <= REL_SLOTS;
+};
+
+template <class VT, class BX>
+struct VLds {
+  using value_type = VT;
+  const VT* p;
+  __device__ __forceinline__ VT load(uint32_t voff, uint32_t soff) const {
+    return *reinterpret_cast<const VT*>(reinterpret_cast<const char*>(p) + voff + soff);
+  }
+  template <int D>
+  __device__ __forceinline__ uint32_t step(const DevProblem&) const {
+    return (uint32_t)(BX::S[D] * (int)sizeof(VT));
+  }
+};
+
+#define STAGE_BLOCK 256
+
+template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP>
+__global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const VI* __restrict__ Vin,
+                                                             VO* __restrict__ Vout,
+                                                             const uint8_t* __restrict__ label,
+                                                             int16_t* __restrict__ pol, const MT* __restrict__ rm) {
+  using BX = StageBox<SH>;
+  constexpr int N = 5;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int blo[N];
+  VI* box = reinterpret_cast<VI*>(smem);
+  MT* ll = reinterpret_cast<MT*>(smem + ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15)) + threadIdx.x;
+  const int t = threadIdx.x;
+  int j[N];
+  {
+    uint32_t r = xcd_block(blockIdx.x, gridDim.x);
+#pragma unroll
+    for (int d = N - 1; d >= 1; --d) {
+      const uint32_t td = (uint32_t)P.count[d] / 4u;
+      const uint32_t c = r % td;
+      r /= td;
+      j[d] = (int)(c * 4u);
+    }
+    j[0] = (int)r;
+    j[4] += t & 3;
+    j[3] += (t >> 2) & 3;
+    j[2] += (t >> 4) & 3;
+    j[1] += t >> 6;
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) s += (uint32_t)j[d] * (uint32_t)P.stride[d];
+  // this thread's cell of a box plane (dims 2..4) and its offset in V
+  constexpr int C3C4 = BX::C[3] * BX::C[4];
+  const bool stager = t < BX::PLANE;
+  const uint32_t gt = (uint32_t)(t / C3C4) * (uint32_t)P.stride[2] +
+                      (uint32_t)((t / BX::C[4]) % BX::C[3]) * (uint32_t)P.stride[3] + (uint32_t)(t % BX::C[4]);
+  const bool free = label[s] == LBL_FREE;
+  if (!free) {
+    Vout[s] = (label[s] == LBL_ONE) ? VO(1) : VO(0);
+    if (pol) pol[s] = -1;
+  }
+  int cx[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    int v = 0;
+    for (int k = 0; k < P.mctx_n[i]; ++k) {
+      int jk = j[0];
+#pragma unroll
+      for (int d = 1; d < N; ++d)
+        if (d == P.mctx[i][k]) jk = j[d];
+      v += jk * P.mmult[i][k];
+    }
+    cx[i] = v;
+  }
+  const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
+  const VLds<VI, BX> vl{box};
+  FixedRow<SH, MT> R;
+  InputWalk iw;
+  iw.reset();
+  AT best = AT(-1);
+  int arg = 0;
+  for (int u = 0; u < P.n_u; ++u) {
+    uint32_t base = 0;
+    memo_load<0, SH, MT>(P, iw, cx, rm, R, base);
+    // every thread has passed the previous input's second barrier, so
+    // blo and the box are no longer read
+    if (t == 0) {
+#pragma unroll
+      for (int d = 0; d < N; ++d) blo[d] = min((int)R.o[d], P.count[d] - BX::C[d]);
+    }
+    __syncthreads();
+    int bl[N];
+    uint32_t gb = 0;
+#pragma unroll
+    for (int d = 0; d < N; ++d) {
+      bl[d] = blo[d];
+      gb += (uint32_t)bl[d] * (uint32_t)P.stride[d];
+    }
+    if (stager) {
+      VI v[BX::PLANES];
+#pragma unroll
+      for (int p = 0; p < BX::PLANES; ++p)
+        v[p] = vb.load((gb + gt) * (uint32_t)sizeof(VI),
+                       ((uint32_t)(p / BX::C[1]) * (uint32_t)P.stride[0] +
+                        (uint32_t)(p % BX::C[1]) * (uint32_t)P.stride[1]) * (uint32_t)sizeof(VI));
+#pragma unroll
+      for (int p = 0; p < BX::PLANES; ++p) box[p * BX::PLANE + t] = v[p];
+    }
+#pragma unroll
+    for (int d = 0; d < SH::BL; ++d)
+#pragma unroll
+      for (int k = 0; k < SH::LMAX; ++k)
+        if (k < SH::L[d]) ll[(d * SH::LMAX + k) * STAGE_BLOCK] = R.m[d][k];
+    __syncthreads();
+    if (free) {
+      bool in = true;
+      uint32_t lo = 0;
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        const int o = (int)R.o[d] - bl[d];
+        in = in && o >= 0 && o + SH::L[d] <= BX::C[d];
+        lo += (uint32_t)o * (uint32_t)BX::S[d];
+      }
+      AT q;
+      if (in)
+        q = contract_fixed<0, SH, MT, AT, VLds<VI, BX>, COMP, STAGE_BLOCK>(P, R, vl, lo * (uint32_t)sizeof(VI), 0u, ll);
+      else
+        q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP, STAGE_BLOCK>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
+      if (q > best) {
+        best = q;
+        arg = u;
+      }
+    }
+    iw.next(P);
+  }
+  if (free) {
+    Vout[s] = VO(best);
+    if (pol) pol[s] = (int16_t)arg;
+  }
+}
+
+template <int KIND, class SH, class MT, class VI>
+static size_t stage_lds_bytes() {
+  using BX = StageBox<SH>;
+  return ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) + (size_t)SH::BL * SH::LMAX * sizeof(MT) * STAGE_BLOCK;
 }
 
 // ------------------------------------------------------------- launchers
@@ -893,6 +1073,18 @@ struct FixedLaunch {
     if constexpr (SH::LMAX <= REL_SLOTS) {
       if (!tailmax && tables && P.tables == 2) {
       const MT* rm = (const MT*)tables;
+      if constexpr (Staged<KIND, SH>::value) {
+        using BX = StageBox<SH>;
+        bool ok = true;
+        for (int d = 0; d < SH::N; ++d) ok = ok && P.count[d] >= BX::C[d] && (d == 0 || P.count[d] % 4 == 0);
+        if (ok) {
+          const dim3 gs((unsigned)(P.n_x / STAGE_BLOCK)), bs(STAGE_BLOCK);
+          const size_t slds = stage_lds_bytes<KIND, SH, MT, VI>();
+          hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP>), gs, bs, slds, st, P, (const VI*)Vin,
+                             (VO*)Vout, label, pol, rm);
+          return;
+        }
+      }
       const size_t lds = (size_t)(SH::BL > 0 ? SH::BL : 1) * SH::LMAX * sizeof(MT) * FIX_BLOCK;
       hipLaunchKernelGGL((k_sweep_memo<KIND, SH, MT, AT, VI, VO, COMP>), g, b, lds, st, P, (const VI*)Vin, (VO*)Vout,
                          label, pol, rm);

@@ -41,6 +41,14 @@ def _room_small(**kw):
     return p.with_(lo=lo, h=h, count=cnt, horizon=kw.pop("horizon", 6), name="room-patch", **kw)
 
 
+def _room8(**kw):
+    # the room workload's cell width, noise and cutoff on an 8^5 grid: whole
+    # 1 x 4 x 4 x 4 x 4 tiles, so the memoised steps stage V boxes in LDS
+    p = W.room5d()
+    lo, h, cnt = W.tiling((19.6,) * 5, (20.4,) * 5, (8,) * 5)
+    return p.with_(lo=lo, h=h, count=cnt, horizon=kw.pop("horizon", 6), name="room-8^5", **kw)
+
+
 CASES = {
     "linear2d-full-fp64-stored": lambda: W.linear2d(precision="fp64", mode="stored"),
     "linear2d-full-fp64-otf": lambda: W.linear2d(precision="fp64", mode="otf"),
@@ -53,6 +61,11 @@ CASES = {
     "room-patch-fp32-otf": lambda: _room_small(precision="fp32"),
     "room-patch-fp64-otf": lambda: _room_small(precision="fp64"),
     "room-patch-fp64-stored": lambda: _room_small(precision="fp64", mode="stored"),
+    "room-8^5-fp32-otf": lambda: _room8(precision="fp32"),
+    "room-8^5-fp64-otf": lambda: _room8(precision="fp64"),
+    # neighbour coupling 0.25: about 4% of the (state, input) windows of a
+    # tile fall outside its staged box and are gathered from V instead
+    "room-8^5-coupled-fp32": lambda: _room8(precision="fp32", params=(0.25, 0.005, 0.01, -1.0, 50.0)),
     "vehicle7-small-fp32": lambda: W.vehicle7d(cells=4, horizon=4).with_(u_count=(3, 3)),
     "vehicle7-small-fp64": lambda: W.vehicle7d(cells=4, horizon=4, precision="fp64").with_(u_count=(3, 3)),
     "linear2d-safebox-fp32": lambda: W.linear2d(cells=37, precision="fp32", mode="otf").with_(
@@ -188,7 +201,8 @@ def test_full_size_separable_5d(orc):
 
 
 @pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "room-patch-fp32-otf",
-                                  "linear2d-full-fp32-otf", "room-patch-fp64-otf"])
+                                  "linear2d-full-fp32-otf", "room-patch-fp64-otf", "room-8^5-fp32-otf",
+                                  "room-8^5-fp64-otf", "room-8^5-coupled-fp32"])
 def test_fixed_shape_kernel_matches_generic(name):
     """The compiled-window-shape sweep does the generic sweep's arithmetic in
     the same order: results are bitwise equal."""

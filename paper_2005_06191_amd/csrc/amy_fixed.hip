@@ -723,9 +723,10 @@ __device__ __forceinline__ int origin_of(MT v) {
 }
 
 // Entry e is the record rm[e*REC .. e*REC+REC): the masses of its window, zeros,
-// and the window origin's bits in the last slot.
+// and the window origin's bits in the last slot; wg[2e], wg[2e+1]: its FP64
+// kept-window and grid masses (the per-row tail's factors).
 template <int KIND, int N, class MT, int REC>
-__global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict__ rm) {
+__global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict__ rm, double* __restrict__ wg) {
   const int e = blockIdx.x * 64 + threadIdx.x;
   if (e >= P.rel_entries) return;
   int i = 0;
@@ -768,6 +769,15 @@ __global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict_
   MT* dst = rm + (int64_t)e * REC;
 #pragma unroll
   for (int k = 0; k < REC; ++k) dst[k] = t[k];
+  double wm, gm;
+  win_grid_mass(P, i, w, wm, gm);
+  wg[2 * (int64_t)e] = wm;
+  wg[2 * (int64_t)e + 1] = gm;
+}
+
+// Byte offset of the memoised tables' FP64 window and grid masses.
+__host__ __device__ inline uint64_t memo_wg_offset(const DevProblem& P, int rec, uint64_t msz) {
+  return ((uint64_t)P.rel_entries * (uint64_t)rec * msz + 255) & ~255ull;
 }
 
 template <class MT, int REC>
@@ -775,10 +785,14 @@ struct alignas(REC * sizeof(MT)) MemoRec {
   MT v[REC];
 };
 
-// Every dimension's record for the current input: masses and origin.
-template <int I, class SH, class MT>
+// Every dimension's record for the current input: masses and origin.  TAIL:
+// also the products of the dimensions' FP64 window and grid masses, in
+// dimension order (as the per-state path forms them).
+template <int I, class SH, class MT, bool TAIL = false>
 __device__ __forceinline__ void memo_load(const DevProblem& P, const InputWalk& iw, const int* cx,
-                                          const MT* __restrict__ rm, FixedRow<SH, MT>& R, uint32_t& base) {
+                                          const MT* __restrict__ rm, FixedRow<SH, MT>& R, uint32_t& base,
+                                          const double* __restrict__ wg = nullptr, double* win = nullptr,
+                                          double* grid = nullptr) {
   if constexpr (I < SH::N) {
     constexpr int REC = amy_memo_rec(SH::LMAX);
     int c = 0;
@@ -790,7 +804,11 @@ __device__ __forceinline__ void memo_load(const DevProblem& P, const InputWalk& 
     for (int k = 0; k < SH::L[I]; ++k) R.m[I][k] = r.v[k];
     R.o[I] = (uint32_t)origin_of<MT>(r.v[REC - 1]);
     base += R.o[I] * (uint32_t)P.stride[I];
-    memo_load<I + 1, SH, MT>(P, iw, cx, rm, R, base);
+    if constexpr (TAIL) {
+      *win *= wg[2 * (int64_t)e];
+      *grid *= wg[2 * (int64_t)e + 1];
+    }
+    memo_load<I + 1, SH, MT, TAIL>(P, iw, cx, rm, R, base, wg, win, grid);
   }
 }
 
@@ -929,11 +947,14 @@ struct VLds {
 
 #define STAGE_BLOCK 256
 
-template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP>
+// TAIL: also the largest per-row FP64 tail over the launch into *tailmax.
+template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
 __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const VI* __restrict__ Vin,
                                                              VO* __restrict__ Vout,
                                                              const uint8_t* __restrict__ label,
-                                                             int16_t* __restrict__ pol, const MT* __restrict__ rm) {
+                                                             int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                             const double* __restrict__ wg,
+                                                             unsigned long long* __restrict__ tailmax) {
   using BX = StageBox<SH>;
   constexpr int N = 5;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -990,9 +1011,14 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
   iw.reset();
   AT best = AT(-1);
   int arg = 0;
+  double tmax = 0.0;
   for (int u = 0; u < P.n_u; ++u) {
     uint32_t base = 0;
-    memo_load<0, SH, MT>(P, iw, cx, rm, R, base);
+    double win = 1.0, grid = 1.0;
+    memo_load<0, SH, MT, TAIL>(P, iw, cx, rm, R, base, wg, &win, &grid);
+    if constexpr (TAIL) {
+      if (free) tmax = fmax(tmax, grid - win);
+    }
     // every thread has passed the previous input's second barrier, so
     // blo and the box are no longer read
     if (t == 0) {
@@ -1048,6 +1074,11 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
     Vout[s] = VO(best);
     if (pol) pol[s] = (int16_t)arg;
   }
+  if constexpr (TAIL) {
+    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+    if ((threadIdx.x & 63) == 0 && tmax > 0.0)
+      atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+  }
 }
 
 template <int KIND, class SH, class MT, class VI>
@@ -1071,20 +1102,27 @@ struct FixedLaunch {
                  unsigned long long* tailmax, const void* tables, hipStream_t st) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
     if constexpr (SH::LMAX <= REL_SLOTS) {
-      if (!tailmax && tables && P.tables == 2) {
-      const MT* rm = (const MT*)tables;
       if constexpr (Staged<KIND, SH>::value) {
         using BX = StageBox<SH>;
-        bool ok = true;
+        bool ok = tables && P.tables == 2;
         for (int d = 0; d < SH::N; ++d) ok = ok && P.count[d] >= BX::C[d] && (d == 0 || P.count[d] % 4 == 0);
         if (ok) {
+          const MT* rm = (const MT*)tables;
+          const double* wg =
+              (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(SH::LMAX), sizeof(MT)));
           const dim3 gs((unsigned)(P.n_x / STAGE_BLOCK)), bs(STAGE_BLOCK);
           const size_t slds = stage_lds_bytes<KIND, SH, MT, VI>();
-          hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP>), gs, bs, slds, st, P, (const VI*)Vin,
-                             (VO*)Vout, label, pol, rm);
+          if (tailmax)
+            hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP, true>), gs, bs, slds, st, P,
+                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+          else
+            hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP, false>), gs, bs, slds, st, P,
+                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
           return;
         }
       }
+      if (!tailmax && tables && P.tables == 2) {
+      const MT* rm = (const MT*)tables;
       const size_t lds = (size_t)(SH::BL > 0 ? SH::BL : 1) * SH::LMAX * sizeof(MT) * FIX_BLOCK;
       hipLaunchKernelGGL((k_sweep_memo<KIND, SH, MT, AT, VI, VO, COMP>), g, b, lds, st, P, (const VI*)Vin, (VO*)Vout,
                          label, pol, rm);
@@ -1113,8 +1151,9 @@ struct FixedLaunch {
     if (SH::LMAX > REL_SLOTS) return hipErrorInvalidValue;  // the host never plans it
     const dim3 g((unsigned)((P.rel_entries + 63) / 64)), b(64);
     constexpr int REC = amy_memo_rec(SH::LMAX);
-    if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double, REC>), g, b, 0, st, P, (double*)tables);
-    else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float, REC>), g, b, 0, st, P, (float*)tables);
+    double* wg = (double*)((char*)tables + memo_wg_offset(P, REC, f64 ? 8 : 4));
+    if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double, REC>), g, b, 0, st, P, (double*)tables, wg);
+    else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float, REC>), g, b, 0, st, P, (float*)tables, wg);
     return hipGetLastError();
   }
 };

@@ -482,7 +482,8 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
     if (pl->dev.tables == 2) {
       int lmax = 1;
       for (int i = 0; i < pl->dev.n; ++i) lmax = pl->dev.L[i] > lmax ? pl->dev.L[i] : lmax;
-      pl->ws_bytes += (ne * (uint64_t)amy_memo_rec(lmax) * msz + 255) & ~255ull;
+      // records, then each entry's FP64 kept-window and grid masses
+      pl->ws_bytes += ((ne * (uint64_t)amy_memo_rec(lmax) * msz + 255) & ~255ull) + ((ne * 16 + 255) & ~255ull);
     } else {
       pl->ws_bytes += ((ne * 8 * msz + 255) & ~255ull) + ((ne * 4 + 255) & ~255ull);
     }

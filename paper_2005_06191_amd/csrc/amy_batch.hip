@@ -72,11 +72,9 @@ __device__ __forceinline__ void run_otf_g(const BatchSys& B, uint32_t s, int t, 
 
 template <int KIND, int N, bool F64>
 __device__ __forceinline__ void run_otf(const BatchSys& B, uint32_t tile, int t, unsigned char* smem) {
-  switch (B.P.grp_g) {
-    case 16: run_otf_g<KIND, N, 16, F64>(B, tile, t, smem); return;
-    case 64: run_otf_g<KIND, N, 64, F64>(B, tile, t, smem); return;
-    default: run_otf_g<KIND, N, 1, F64>(B, tile * BATCH_BLOCK + (threadIdx.x & 63), t, smem); return;
-  }
+  // the host plans every batched system as LANES (1) or GROUP64 (64)
+  if (B.P.grp_g == 64) run_otf_g<KIND, N, 64, F64>(B, tile, t, smem);
+  else run_otf_g<KIND, N, 1, F64>(B, tile * BATCH_BLOCK + (threadIdx.x & 63), t, smem);
 }
 
 template <int N, bool F64>

@@ -14,6 +14,34 @@
 
 static inline uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+// A system in a batched launch runs one of the two run-time-window variants
+// compiled into the batched kernel, LANES or GROUP64: every variant computes
+// the same bits, and leaving the others out keeps the batched kernel's
+// register budget (and so its occupancy) at that of those two.  The
+// compiled-shape variants become LANES, GROUP16 becomes GROUP64, and stored
+// rows are walked 64 states per tile whatever the variant.
+amy_status amy_batch_normalise(const amy_problem* p, Plan* pl) {
+  DevProblem& D = pl->dev;
+  if (pl->mode == AMY_MODE_STORED) {
+    D.grp_g = 1;
+    return AMY_OK;
+  }
+  if (D.variant == AMY_VARIANT_FIXED || D.variant == AMY_VARIANT_FACTORED) {
+    D.variant = AMY_VARIANT_LANES;
+    D.rel_entries = 0;
+  }
+  if (D.variant == AMY_VARIANT_GROUP16) {
+    amy_problem q = *p;
+    q.mode = AMY_MODE_OTF;
+    q.variant = AMY_VARIANT_GROUP64;
+    const amy_status st = amy_resolve(&q, 0, pl);
+    if (st != AMY_OK) return st;
+  }
+  if (D.grp_g != 1 && D.grp_g != 64)
+    return amy_fail(AMY_E_UNSUPPORTED, "batched launch: %d lanes per state", (int)D.grp_g);
+  return AMY_OK;
+}
+
 amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp) {
   if (!probs || count < 1 || count > AMY_BATCH_MAX)
     return amy_fail(AMY_E_INVALID, "batch of %d systems (1..%d)", count, AMY_BATCH_MAX);
@@ -30,13 +58,8 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
     q.mode = AMY_MODE_OTF;
     if (q.variant == AMY_VARIANT_FIXED || q.variant == AMY_VARIANT_FACTORED) q.variant = AMY_VARIANT_LANES;
     st = amy_resolve(&q, 0, &bp.plans[i]);
+    if (st == AMY_OK) st = amy_batch_normalise(&q, &bp.plans[i]);
     if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
-    // the compiled-shape sweep is not part of the batched kernel; LANES
-    // computes the same bits
-    if (bp.plans[i].dev.variant == AMY_VARIANT_FIXED || bp.plans[i].dev.variant == AMY_VARIANT_FACTORED) {
-      bp.plans[i].dev.variant = AMY_VARIANT_LANES;
-      bp.plans[i].dev.rel_entries = 0;
-    }
     const DevProblem& D = bp.plans[i].dev;
     if (!amy_batch_supports(D.kind, D.n, AMY_MODE_OTF))
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: dynamics kind %d with n=%d is not compiled into the batched kernel",

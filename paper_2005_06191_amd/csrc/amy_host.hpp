@@ -64,6 +64,7 @@ struct BatchTune {
 };
 
 amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp);
+amy_status amy_batch_normalise(const amy_problem* p, Plan* pl);
 amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStream_t hs, char* ws,
                          double* const* V_out, int16_t* const* policy_out, bool want_tail, const BatchTune& tune,
                          float* ms_out);

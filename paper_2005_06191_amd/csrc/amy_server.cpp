@@ -314,8 +314,10 @@ void amy_server::run() {
         const int per_tile = 64 / std::max(1, (int)pl.dev.grp_g);
         B.tiles = (int32_t)((pl.dev.n_x + per_tile - 1) / per_tile);
         meta[n + 2] = meta[n + 1] + B.tiles;
-        lds = std::max(lds, pl.dev.grp_g > 1 ? pl.dev.lds_bytes_group : pl.dev.lds_bytes_tail);
-        if (pl.mode != AMY_MODE_STORED) fs = std::max(fs, amy_batch_family_set(pl.dev.kind, pl.dev.n));
+        if (pl.mode != AMY_MODE_STORED) {
+          lds = std::max(lds, pl.dev.grp_g > 1 ? pl.dev.lds_bytes_group : pl.dev.lds_bytes_tail);
+          fs = std::max(fs, amy_batch_family_set(pl.dev.kind, pl.dev.n));
+        }
         ++n;
       }
       if (n == 0) continue;
@@ -458,9 +460,13 @@ extern "C" amy_status amy_server_submit(amy_server* s, const amy_problem* p, int
   // launch per step; the rest share the batched step, which runs the
   // run-time-window code (same bits as the compiled-shape sweep)
   r->solo = r->plan.dev.n_x >= SOLO_STATES || !amy_batch_supports(r->plan.dev.kind, r->plan.dev.n, r->plan.mode);
-  if (!r->solo && (r->plan.dev.variant == AMY_VARIANT_FIXED || r->plan.dev.variant == AMY_VARIANT_FACTORED)) {
-    r->plan.dev.variant = AMY_VARIANT_LANES;
-    r->plan.dev.rel_entries = 0;
+  if (!r->solo) {
+    q.mode = r->plan.mode;
+    st = amy_batch_normalise(&q, &r->plan);
+    if (st != AMY_OK) {
+      delete r;
+      return st;
+    }
   }
   r->off_v = al256(r->plan.ws_bytes);
   r->off_pol = al256(r->off_v + (uint64_t)r->plan.dev.n_x * 8);

@@ -92,6 +92,17 @@ __device__ __forceinline__ void vbuf_run(const VBuf<VT>& vb, uint32_t voff, uint
   for (; t < n; ++t) v[t] = vb.load(voff + (uint32_t)(t * sizeof(VT)), soff);
 }
 
+// n consecutive cells of V from a V source, as wide as the source allows.
+template <int n, class VT>
+__device__ __forceinline__ void v_run(const VBuf<VT>& vb, uint32_t voff, uint32_t soff, VT* v) {
+  vbuf_run<VT, n>(vb, voff, soff, v);
+}
+template <int n, class VS>
+__device__ __forceinline__ void v_run(const VS& vs, uint32_t voff, uint32_t soff, typename VS::value_type* v) {
+#pragma unroll
+  for (int t = 0; t < n; ++t) v[t] = vs.load(voff + (uint32_t)(t * sizeof(typename VS::value_type)), soff);
+}
+
 // 1-D masses of an L-slot window into registers (same edges as dim_table).
 template <class MT, int L>
 __device__ __forceinline__ void fixed_table(const DevProblem& P, int i, const Win& w, MT* m) {
@@ -164,6 +175,10 @@ __device__ __forceinline__ AT contract_fixed(const DevProblem& P, const FixedRow
 
 // LL > 0: the loop levels' masses are also in the thread's LDS slot ll
 // ([level * LMAX + k][thread], LL threads) and are read from there by index.
+template <int D, class SH, class MT, class AT, bool COMP, int LL>
+__device__ __forceinline__ void accum_step(const FixedRow<SH, MT>& R, int k, AT inner, AT& acc, AT& c,
+                                           const MT* ll);
+
 template <int D, class SH, class MT, class AT, class VS, bool COMP, int LL = 0>
 __device__ __forceinline__ void contract_step(const DevProblem& P, const FixedRow<SH, MT>& R,
                                               const VS& vb, uint32_t voff, uint32_t soff, int k,
@@ -175,6 +190,13 @@ __device__ __forceinline__ void contract_step(const DevProblem& P, const FixedRo
     inner = contract_fixed<D + 1, SH, MT, AT, VS, COMP, LL>(P, R, vb, voff,
                                                             soff + (uint32_t)k * vb.template step<D>(P), ll);
   }
+  accum_step<D, SH, MT, AT, COMP, LL>(R, k, inner, acc, c, ll);
+}
+
+// acc += mass of slot k of level D times inner (compensated at level 0).
+template <int D, class SH, class MT, class AT, bool COMP, int LL>
+__device__ __forceinline__ void accum_step(const FixedRow<SH, MT>& R, int k, AT inner, AT& acc, AT& c,
+                                           const MT* ll) {
   // mass of slot k; in a loop level k is a uniform register, so pick it
   // with selects (or from LDS) rather than an indexed register access
   MT mk;
@@ -207,6 +229,12 @@ __device__ __forceinline__ AT contract_fixed(const DevProblem& P, const FixedRow
   if constexpr (D < SH::BL) {
 #pragma clang loop unroll(disable)
     for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VS, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);
+  } else if constexpr (D == SH::N - 1) {
+    // the innermost run of L cells is contiguous in V: load it whole
+    typename VS::value_type v[L];
+    v_run<L>(vb, voff, soff, v);
+#pragma unroll
+    for (int k = 0; k < L; ++k) accum_step<D, SH, MT, AT, COMP, LL>(R, k, AT(v[k]), acc, c, ll);
   } else {
 #pragma unroll
     for (int k = 0; k < L; ++k) contract_step<D, SH, MT, AT, VS, COMP, LL>(P, R, vb, voff, soff, k, acc, c, ll);

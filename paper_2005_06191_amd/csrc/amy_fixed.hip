@@ -1115,6 +1115,182 @@ static size_t stage_lds_bytes() {
   return ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) + (size_t)SH::BL * SH::LMAX * sizeof(MT) * STAGE_BLOCK;
 }
 
+// ----------------------------------------------- staged planes (7-D)
+//
+// The vehicle's grid has 8 x 8 cells in its last two dimensions (yaw rate,
+// slip angle), so one such plane of V is 64 contiguous values.  A workgroup
+// of 128 threads takes the two planes of states at cells 2b, 2b + 1 of
+// dimension 4 (the other coordinates fixed); their windows share the
+// origins of dimensions 0 .. 3 (those means do not read the plane's
+// coordinates) and spread by at most 2 cells in dimension 4 (the heading
+// moves with the yaw rate).  For each input the workgroup copies the
+// L0 x L1 x L2 x L3 x (L4 + 2) planes that hold the windows into LDS, one
+// 256-byte plane per wave and load, and contracts from there.  As for the
+// room, the box starts at the first state's origin clamped to the grid, a
+// window outside it is gathered from V, and the result is bitwise that of
+// the gather sweep.
+template <class SH>
+struct PlaneBox {
+  static_assert(SH::N == 7, "plane box: 7-D shapes");
+  static constexpr int C[7] = {SH::L[0], SH::L[1], SH::L[2], SH::L[3], SH::L[4] + 2, 8, 8};
+  static constexpr int S[7] = {C[1] * C[2] * C[3] * C[4] * 64, C[2] * C[3] * C[4] * 64, C[3] * C[4] * 64,
+                               C[4] * 64, 64, 8, 1};
+  static constexpr int PLANES = C[0] * C[1] * C[2] * C[3] * C[4];
+  static constexpr int SIZE = PLANES * 64;
+};
+
+template <int KIND, class SH>
+struct Planed {
+  static constexpr bool value = KIND == AMY_DYN_VEHICLE7_ && SH::N == 7 && SH::LMAX <= REL_SLOTS;
+};
+
+#define PLANE_BLOCK 128
+
+template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+__global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const VI* __restrict__ Vin,
+                                                             VO* __restrict__ Vout,
+                                                             const uint8_t* __restrict__ label,
+                                                             int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                             const double* __restrict__ wg,
+                                                             unsigned long long* __restrict__ tailmax) {
+  using BX = PlaneBox<SH>;
+  constexpr int N = 7;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int blo[N];
+  VI* box = reinterpret_cast<VI*>(smem);
+  MT* ll = reinterpret_cast<MT*>(smem + ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15)) + threadIdx.x;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  int j[N];
+  {
+    uint32_t r = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t t4 = (uint32_t)P.count[4] / 2u;
+    j[4] = (int)(r % t4) * 2 + wave;
+    r /= t4;
+#pragma unroll
+    for (int d = 3; d >= 0; --d) {
+      const uint32_t c = (uint32_t)P.count[d];
+      j[d] = (int)(r % c);
+      r /= c;
+    }
+    j[5] = lane >> 3;
+    j[6] = lane & 7;
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (int d = 0; d < N; ++d) s += (uint32_t)j[d] * (uint32_t)P.stride[d];
+  const bool free = label[s] == LBL_FREE;
+  if (!free) {
+    Vout[s] = (label[s] == LBL_ONE) ? VO(1) : VO(0);
+    if (pol) pol[s] = -1;
+  }
+  int cx[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    int v = 0;
+    for (int k = 0; k < P.mctx_n[i]; ++k) {
+      int jk = j[0];
+#pragma unroll
+      for (int d = 1; d < N; ++d)
+        if (d == P.mctx[i][k]) jk = j[d];
+      v += jk * P.mmult[i][k];
+    }
+    cx[i] = v;
+  }
+  const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
+  const VLds<VI, BX> vl{box};
+  FixedRow<SH, MT> R;
+  InputWalk iw;
+  iw.reset();
+  AT best = AT(-1);
+  int arg = 0;
+  double tmax = 0.0;
+  for (int u = 0; u < P.n_u; ++u) {
+    uint32_t base = 0;
+    double win = 1.0, grid = 1.0;
+    memo_load<0, SH, MT, TAIL>(P, iw, cx, rm, R, base, wg, &win, &grid);
+    if constexpr (TAIL) {
+      if (free) tmax = fmax(tmax, grid - win);
+    }
+    // every thread has passed the previous input's second barrier
+    if (t == 0) {
+#pragma unroll
+      for (int d = 0; d < 5; ++d) blo[d] = min((int)R.o[d], P.count[d] - BX::C[d]);
+    }
+    __syncthreads();
+    int bl[N];
+    uint32_t gb = 0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      bl[d] = blo[d];
+      gb += (uint32_t)bl[d] * (uint32_t)P.stride[d];
+    }
+    bl[5] = bl[6] = 0;
+    // wave w stages the planes with box coordinate w in dimension 0 (the
+    // box is 2 cells wide there); plane i of a wave has fixed coordinates
+    // (r1 .. r4), so its offset is a fixed combination of the strides.  Each
+    // plane is 64 consecutive values of V.  Fully unrolled, CH loads in
+    // flight, then their LDS writes, and a scheduling barrier so that the
+    // next chunk's loads are not hoisted above them (registers).
+    static_assert(BX::C[0] == 2, "one wave per half of the box along dimension 0");
+    constexpr int PER = BX::PLANES / 2, CH = 15;
+    static_assert(PER % CH == 0, "whole chunks");
+    const uint32_t gw = (gb + (uint32_t)wave * (uint32_t)P.stride[0] + (uint32_t)lane) * (uint32_t)sizeof(VI);
+    VI* bw = box + wave * PER * 64 + lane;
+#pragma unroll
+    for (int q0 = 0; q0 < PER; q0 += CH) {
+      VI v[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int i = q0 + q;
+        const int r4 = i % BX::C[4], r3 = (i / BX::C[4]) % BX::C[3], r2 = (i / (BX::C[4] * BX::C[3])) % BX::C[2];
+        const int r1 = i / (BX::C[4] * BX::C[3] * BX::C[2]);
+        const uint32_t po = (uint32_t)r1 * (uint32_t)P.stride[1] + (uint32_t)r2 * (uint32_t)P.stride[2] +
+                            (uint32_t)r3 * (uint32_t)P.stride[3] + (uint32_t)r4 * (uint32_t)P.stride[4];
+        v[q] = vb.load(gw, po * (uint32_t)sizeof(VI));
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q) bw[(q0 + q) * 64] = v[q];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int d = 0; d < SH::BL; ++d)
+#pragma unroll
+      for (int k = 0; k < SH::LMAX; ++k)
+        if (k < SH::L[d]) ll[(d * SH::LMAX + k) * PLANE_BLOCK] = R.m[d][k];
+    __syncthreads();
+    if (free) {
+      bool in = true;
+      uint32_t lo = 0;
+#pragma unroll
+      for (int d = 0; d < N; ++d) {
+        const int o = (int)R.o[d] - bl[d];
+        in = in && o >= 0 && o + SH::L[d] <= BX::C[d];
+        lo += (uint32_t)o * (uint32_t)BX::S[d];
+      }
+      AT q;
+      if (in)
+        q = contract_fixed<0, SH, MT, AT, VLds<VI, BX>, COMP, PLANE_BLOCK>(P, R, vl, lo * (uint32_t)sizeof(VI), 0u, ll);
+      else
+        q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP, PLANE_BLOCK>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
+      if (q > best) {
+        best = q;
+        arg = u;
+      }
+    }
+    iw.next(P);
+  }
+  if (free) {
+    Vout[s] = VO(best);
+    if (pol) pol[s] = (int16_t)arg;
+  }
+  if constexpr (TAIL) {
+    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+    if ((threadIdx.x & 63) == 0 && tmax > 0.0)
+      atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+  }
+}
+
 // ------------------------------------------------------------- launchers
 
 template <int KIND, class SH>
@@ -1130,6 +1306,26 @@ struct FixedLaunch {
                  unsigned long long* tailmax, const void* tables, hipStream_t st) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
     if constexpr (SH::LMAX <= REL_SLOTS) {
+      if constexpr (Planed<KIND, SH>::value && sizeof(VI) == 4) {
+        using BX = PlaneBox<SH>;
+        bool ok = tables && P.tables == 2 && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0;
+        for (int d = 0; d < 5; ++d) ok = ok && P.count[d] >= BX::C[d];
+        if (ok) {
+          const MT* rm = (const MT*)tables;
+          const double* wg =
+              (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(SH::LMAX), sizeof(MT)));
+          const dim3 gs((unsigned)(P.n_x / PLANE_BLOCK)), bs(PLANE_BLOCK);
+          const size_t slds = ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) +
+                              (size_t)SH::BL * SH::LMAX * sizeof(MT) * PLANE_BLOCK;
+          if (tailmax)
+            hipLaunchKernelGGL((k_sweep_plane<KIND, SH, MT, AT, VI, VO, COMP, true>), gs, bs, slds, st, P,
+                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+          else
+            hipLaunchKernelGGL((k_sweep_plane<KIND, SH, MT, AT, VI, VO, COMP, false>), gs, bs, slds, st, P,
+                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+          return;
+        }
+      }
       if constexpr (Staged<KIND, SH>::value) {
         using BX = StageBox<SH>;
         bool ok = tables && P.tables == 2;

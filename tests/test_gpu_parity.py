@@ -49,6 +49,15 @@ def _room8(**kw):
     return p.with_(lo=lo, h=h, count=cnt, horizon=kw.pop("horizon", 6), name="room-8^5", **kw)
 
 
+def _vehicle_planes(**kw):
+    # the vehicle workload's cell widths, noise and cutoff on a 2x2x3x3x6 x 8x8
+    # sub-box: whole yaw-rate / slip-angle planes, so the memoised steps stage
+    # planes of V in LDS
+    p = W.vehicle7d()
+    return p.with_(lo=(-2.5, -2.5, -0.15, -0.75, -0.225, -0.4, -0.04), count=(2, 2, 3, 3, 6, 8, 8),
+                   horizon=kw.pop("horizon", 4), u_count=(3, 3), name="vehicle7-planes", **kw)
+
+
 CASES = {
     "linear2d-full-fp64-stored": lambda: W.linear2d(precision="fp64", mode="stored"),
     "linear2d-full-fp64-otf": lambda: W.linear2d(precision="fp64", mode="otf"),
@@ -66,6 +75,11 @@ CASES = {
     # neighbour coupling 0.25: about 4% of the (state, input) windows of a
     # tile fall outside its staged box and are gathered from V instead
     "room-8^5-coupled-fp32": lambda: _room8(precision="fp32", params=(0.25, 0.005, 0.01, -1.0, 50.0)),
+    "vehicle7-planes-fp32": lambda: _vehicle_planes(precision="fp32"),
+    # time step 0.3: about 7% of the windows spread past the staged planes
+    # in the heading and are gathered from V instead
+    "vehicle7-planes-tau0.3-fp32": lambda: _vehicle_planes(precision="fp32",
+                                                           params=(0.3,) + W.VEHICLE7_BMW320I[1:]),
     "vehicle7-small-fp32": lambda: W.vehicle7d(cells=4, horizon=4).with_(u_count=(3, 3)),
     "vehicle7-small-fp64": lambda: W.vehicle7d(cells=4, horizon=4, precision="fp64").with_(u_count=(3, 3)),
     "linear2d-safebox-fp32": lambda: W.linear2d(cells=37, precision="fp32", mode="otf").with_(
@@ -202,7 +216,8 @@ def test_full_size_separable_5d(orc):
 
 @pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "room-patch-fp32-otf",
                                   "linear2d-full-fp32-otf", "room-patch-fp64-otf", "room-8^5-fp32-otf",
-                                  "room-8^5-fp64-otf", "room-8^5-coupled-fp32"])
+                                  "room-8^5-fp64-otf", "room-8^5-coupled-fp32", "vehicle7-planes-fp32",
+                                  "vehicle7-planes-tau0.3-fp32"])
 def test_fixed_shape_kernel_matches_generic(name):
     """The compiled-window-shape sweep does the generic sweep's arithmetic in
     the same order: results are bitwise equal."""

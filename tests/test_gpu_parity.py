@@ -75,6 +75,9 @@ CASES = {
     # neighbour coupling 0.25: about 4% of the (state, input) windows of a
     # tile fall outside its staged box and are gathered from V instead
     "room-8^5-coupled-fp32": lambda: _room8(precision="fp32", params=(0.25, 0.005, 0.01, -1.0, 50.0)),
+    # states outside the safe box are not free: in the staged sweep they
+    # write their value and still take part in every staging pass
+    "room-8^5-safebox-fp32": lambda: _room8(precision="fp32", safe=W.box((19.65,) * 5, (20.3,) * 5, 5)),
     "vehicle7-planes-fp32": lambda: _vehicle_planes(precision="fp32"),
     # time step 0.3: about 7% of the windows spread past the staged planes
     # in the heading and are gathered from V instead
@@ -216,7 +219,8 @@ def test_full_size_separable_5d(orc):
 
 @pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "room-patch-fp32-otf",
                                   "linear2d-full-fp32-otf", "room-patch-fp64-otf", "room-8^5-fp32-otf",
-                                  "room-8^5-fp64-otf", "room-8^5-coupled-fp32", "vehicle7-planes-fp32",
+                                  "room-8^5-fp64-otf", "room-8^5-coupled-fp32", "room-8^5-safebox-fp32",
+                                  "vehicle7-planes-fp32",
                                   "vehicle7-planes-tau0.3-fp32"])
 def test_fixed_shape_kernel_matches_generic(name):
     """The compiled-window-shape sweep does the generic sweep's arithmetic in

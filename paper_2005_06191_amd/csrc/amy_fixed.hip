@@ -319,43 +319,45 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fixed(DevProblem P, const V
 // a loop (its mass read from LDS per iteration); the levels below it are
 // unrolled with their masses in registers, so every gather of one level-0
 // slice issues back to back.
-template <int D, class SH, int U, class MT, class AT, class VT>
-__device__ __forceinline__ void contract_fac_in(const FixedRow<SH, MT>& R, const VBuf<VT>& vb, uint32_t voff,
-                                                uint32_t soff, const int64_t* stride, AT (&acc)[U]) {
+template <int D, class SH, int U, class MT, class AT, class VS>
+__device__ __forceinline__ void contract_fac_in(const DevProblem& P, const FixedRow<SH, MT>& R, const VS& vb,
+                                                uint32_t voff, uint32_t soff, AT (&acc)[U]) {
+  using VT = typename VS::value_type;
 #pragma unroll
   for (int t = 0; t < U; ++t) acc[t] = AT(0);
 #pragma unroll
   for (int k = 0; k < SH::L[D]; ++k) {
-    const uint32_t sk = soff + (uint32_t)k * (uint32_t)stride[D] * (uint32_t)sizeof(VT);
+    const uint32_t sk = soff + (uint32_t)k * vb.template step<D>(P);
     AT inner[U];
     if constexpr (D == SH::N - 2) {
       VT v[U];
-      vbuf_run<VT, U>(vb, voff, sk, v);
+      v_run<U>(vb, voff, sk, v);
 #pragma unroll
       for (int t = 0; t < U; ++t) inner[t] = AT(v[t]);
     } else {
-      contract_fac_in<D + 1, SH, U, MT, AT, VT>(R, vb, voff, sk, stride, inner);
+      contract_fac_in<D + 1, SH, U, MT, AT, VS>(P, R, vb, voff, sk, inner);
     }
 #pragma unroll
     for (int t = 0; t < U; ++t) acc[t] = fma_(AT(R.m[D][k]), inner[t], acc[t]);
   }
 }
 
-template <class SH, int U, class MT, class AT, class VT, bool COMP>
+template <class SH, int U, class MT, class AT, class VS, bool COMP>
 __device__ __forceinline__ void contract_fac(const DevProblem& P, const FixedRow<SH, MT>& R, const MT* m0,
-                                             const VBuf<VT>& vb, uint32_t voff, AT (&acc)[U]) {
+                                             const VS& vb, uint32_t voff, AT (&acc)[U]) {
+  using VT = typename VS::value_type;
   AT c[U];
 #pragma unroll
   for (int t = 0; t < U; ++t) acc[t] = c[t] = AT(0);
 #pragma clang loop unroll(disable)
   for (int k = 0; k < SH::L[0]; ++k) {
-    const uint32_t soff = (uint32_t)k * (uint32_t)P.stride[0] * (uint32_t)sizeof(VT);
+    const uint32_t soff = (uint32_t)k * vb.template step<0>(P);
     AT inner[U];
     if constexpr (SH::N == 2) {
 #pragma unroll
       for (int t = 0; t < U; ++t) inner[t] = AT(vb.load(voff + (uint32_t)(t * sizeof(VT)), soff));
     } else {
-      contract_fac_in<1, SH, U, MT, AT, VT>(R, vb, voff, soff, P.stride, inner);
+      contract_fac_in<1, SH, U, MT, AT, VS>(P, R, vb, voff, soff, inner);
     }
     const AT mk = AT(m0[k * FIX_BLOCK]);
 #pragma unroll
@@ -473,7 +475,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fac(DevProblem P, const VI*
         const MT* m0 = nullptr;
         fac_outer<0, SH, MT, TAIL>(P, iw, S, t0, mu, R, m0, base, win, grid);
         AT A[U];
-        contract_fac<SH, U, MT, AT, VI, COMP>(P, R, m0, vb, base * (uint32_t)sizeof(VI), A);
+        contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, m0, vb, base * (uint32_t)sizeof(VI), A);
         for (int f = 0; f < nf; ++f, ++u) {
           const int c = f * fm;
           const MT* tp = S.tab + (P.toff[F] + c * LF) * FIX_BLOCK;
@@ -698,7 +700,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_rel(DevProblem P, const VI*
     rel_load<0, SH, MT>(P, iw, j, rm, rlo, R, r);
     rel_place<0, SH, MT>(P, r, t0, R, base);
     AT A[U];
-    contract_fac<SH, U, MT, AT, VI, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
+    contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
     for (int f = 0; f < nf; ++f, ++u) {
       const int g = j[F] + thr[f] - omin;  // A index of the first kept cell
       AT q = AT(0);
@@ -1291,6 +1293,165 @@ __global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const
   }
 }
 
+// ------------------------------------- staged boxes, shared relative tables
+//
+// The unicycle's steps on the shared relative tables, with one workgroup
+// per (x, y) cell: lane t takes heading cell t (at most 64 cells).  Over
+// every heading and input, the x and y windows of that cell start within
+// 3 cells of each other (the drift is at most one cell), so the workgroup
+// copies the 7 x 7 rows of all headings that hold them from V into LDS once
+// per step (each row is contiguous in V) and every input contracts from
+// there.  The box starts at the smallest origin over its lanes and inputs,
+// clamped to the grid; a window outside it is gathered from V.  The order
+// of operations is that of k_sweep_rel, so the bits are the same.
+template <class SH>
+struct RelBox {
+  static_assert(SH::N == 3, "relative-table box: 3-D shapes");
+  static constexpr int C[3] = {SH::L[0] + 2, SH::L[1] + 2, 64};
+  static constexpr int S[3] = {C[1] * 64, 64, 1};
+  static constexpr int ROWS = C[0] * C[1];
+  static constexpr int SIZE = ROWS * 64;
+};
+
+template <int KIND, class SH, int U, class MT, class AT, class VI, class VO, bool COMP>
+__global__ void __launch_bounds__(FIX_BLOCK) k_sweep_relbox(DevProblem P, const VI* __restrict__ Vin,
+                                                            VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                                            int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                            const int32_t* __restrict__ rlo) {
+  using BX = RelBox<SH>;
+  constexpr int N = 3;
+  constexpr int F = N - 1;
+  constexpr int LF = SH::L[F];
+  static_assert(LF <= U && SH::LMAX <= REL_SLOTS, "relative-table sweep shape");
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int fd = P.m - 1, nf = P.ucount[fd], fm = P.rmult[F][fd];
+  VI* box = reinterpret_cast<VI*>(smem);
+  MT* t0 = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI)) + threadIdx.x;
+  MT* thm = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI)) + SH::L[0] * FIX_BLOCK;
+  int32_t* thr = reinterpret_cast<int32_t*>(thm + nf * LF);
+  for (int f = threadIdx.x; f < nf; f += FIX_BLOCK) {
+    const int e = P.rel_off[F] + f * fm;
+#pragma unroll
+    for (int k = 0; k < LF; ++k) thm[f * LF + k] = rm[(int64_t)e * REL_SLOTS + k];
+    thr[f] = rlo[e];
+  }
+  const int lane = threadIdx.x;
+  const int nF = P.count[F];
+  const uint32_t pair = xcd_block(blockIdx.x, gridDim.x);
+  int j[N];
+  j[1] = (int)(pair % (uint32_t)P.count[1]);
+  j[0] = (int)(pair / (uint32_t)P.count[1]);
+  j[F] = lane;
+  const bool valid = lane < nF;
+  const uint32_t s = pair * (uint32_t)nF + (uint32_t)lane;
+  const uint8_t lb = valid ? label[s] : (uint8_t)LBL_ZERO;
+  const bool free = valid && lb == LBL_FREE;
+  if (valid && !free) {
+    Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
+    if (pol) pol[s] = -1;
+  }
+  const int nslow = P.n_u / nf;
+  // the box origin: the smallest x and y window origin over the free lanes
+  // and the slow digits (the fast digit moves only the heading)
+  int lo0 = P.count[0], lo1 = P.count[1];
+  if (free) {
+    InputWalk iw;
+    iw.reset();
+    FixedRow<SH, MT> R;
+    for (int sc = 0; sc < nslow; ++sc) {
+      int r[N];
+      rel_load<0, SH, MT>(P, iw, j, rm, rlo, R, r);
+      lo0 = min(lo0, min(max(r[0], 0), P.count[0] - SH::L[0]));
+      lo1 = min(lo1, min(max(r[1], 0), P.count[1] - SH::L[1]));
+#pragma unroll
+      for (int k = AMY_MAXI - 1; k >= 0; --k) {
+        if (k < fd) {
+          if (++iw.dig[k] < P.ucount[k]) break;
+          iw.dig[k] = 0;
+        }
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo0 = min(lo0, __shfl_xor(lo0, off));
+    lo1 = min(lo1, __shfl_xor(lo1, off));
+  }
+  const int b0 = __builtin_amdgcn_readfirstlane(min(lo0, P.count[0] - BX::C[0]));
+  const int b1 = __builtin_amdgcn_readfirstlane(min(lo1, P.count[1] - BX::C[1]));
+  const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
+  {
+    // rows (x, y) of the box, each the run of all heading cells
+    const uint32_t gl = ((uint32_t)b0 * (uint32_t)P.stride[0] + (uint32_t)b1 * (uint32_t)P.stride[1] +
+                         (uint32_t)min(lane, nF - 1)) * (uint32_t)sizeof(VI);
+    constexpr int CH = 7;
+    static_assert(BX::ROWS % CH == 0, "whole chunks");
+#pragma unroll
+    for (int q0 = 0; q0 < BX::ROWS; q0 += CH) {
+      VI v[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int rx = (q0 + q) / BX::C[1], ry = (q0 + q) % BX::C[1];
+        v[q] = vb.load(gl, ((uint32_t)rx * (uint32_t)P.stride[0] + (uint32_t)ry * (uint32_t)P.stride[1]) *
+                               (uint32_t)sizeof(VI));
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q) box[(q0 + q) * 64 + lane] = v[q];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();
+  if (!free) return;  // one wave per workgroup: no barrier follows
+  const VLds<VI, BX> vl{box};
+  int omin = nF;
+  for (int f = 0; f < nf; ++f) omin = min(omin, min(max(j[F] + thr[f], 0), nF - LF));
+  FixedRow<SH, MT> R;
+  InputWalk iw;
+  iw.reset();
+  AT best = AT(-1);
+  int arg = 0, u = 0;
+  for (int sc = 0; sc < nslow; ++sc) {
+    uint32_t base = (uint32_t)omin;
+    int r[N];
+    rel_load<0, SH, MT>(P, iw, j, rm, rlo, R, r);
+    rel_place<0, SH, MT>(P, r, t0, R, base);
+    const int o0 = min(max(r[0], 0), P.count[0] - SH::L[0]) - b0;
+    const int o1 = min(max(r[1], 0), P.count[1] - SH::L[1]) - b1;
+    AT A[U];
+    if (o0 >= 0 && o0 + SH::L[0] <= BX::C[0] && o1 >= 0 && o1 + SH::L[1] <= BX::C[1])
+      contract_fac<SH, U, MT, AT, VLds<VI, BX>, COMP>(
+          P, R, t0, vl, ((uint32_t)o0 * BX::S[0] + (uint32_t)o1 * BX::S[1] + (uint32_t)omin) * (uint32_t)sizeof(VI), A);
+    else
+      contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
+    for (int f = 0; f < nf; ++f, ++u) {
+      const int g = j[F] + thr[f] - omin;  // A index of the first kept cell
+      AT q = AT(0);
+#pragma unroll
+      for (int k = 0; k < LF; ++k) {
+        const int t = g + k;
+        AT a = A[0];
+#pragma unroll
+        for (int jj = 1; jj < U; ++jj) a = (t == jj) ? A[jj] : a;
+        const bool ok = t >= 0 && t < U && omin + t < nF;
+        const AT qk = fma_(AT(thm[f * LF + k]), a, q);
+        q = ok ? qk : q;
+      }
+      if (q > best) {
+        best = q;
+        arg = u;
+      }
+    }
+#pragma unroll
+    for (int k = AMY_MAXI - 1; k >= 0; --k) {
+      if (k < fd) {
+        if (++iw.dig[k] < P.ucount[k]) break;
+        iw.dig[k] = 0;
+      }
+    }
+  }
+  Vout[s] = VO(best);
+  if (pol) pol[s] = (int16_t)arg;
+}
+
 // ------------------------------------------------------------- launchers
 
 template <int KIND, class SH>
@@ -1414,6 +1575,15 @@ struct FacLaunch {
         const int nf = P.ucount[P.m - 1];
         const size_t lds = (size_t)SH::L[0] * sizeof(MT) * FIX_BLOCK + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) +
                            (size_t)nf * 4;
+        if constexpr (SH::N == 3) {
+          using BX = RelBox<SH>;
+          if (P.count[2] <= 64 && P.count[0] >= BX::C[0] && P.count[1] >= BX::C[1]) {
+            const dim3 gb((unsigned)(P.n_x / P.count[2]));
+            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP>), gb, b,
+                               lds + BX::SIZE * sizeof(VI), st, P, (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
+            return;
+          }
+        }
         hipLaunchKernelGGL((k_sweep_rel<KIND, SH, U, MT, AT, VI, VO, COMP>), g, b, lds, st, P, (const VI*)Vin,
                            (VO*)Vout, label, pol, rm, ro);
         return;

@@ -301,6 +301,88 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fixed(DevProblem P, const V
   }
 }
 
+// FP64 row tails alone, for the first step of a solve whose sweep reads the
+// shared relative tables (that sweep runs after it).  Per state, the cached
+// dimensions' kept-window and grid masses are computed once per input-digit
+// combination into LDS ([2 x slot][lane] doubles, no mass tables), the
+// others per input when their mean changes; each row's products are taken
+// in dimension order with the same window rule and mass routine as the fused
+// first step, so the max is that step's, bit for bit.
+template <int KIND, int N>
+__global__ void __launch_bounds__(FIX_BLOCK) k_tail_cached(DevProblem P, const uint8_t* __restrict__ label,
+                                                           unsigned long long* __restrict__ tailmax) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* wg = reinterpret_cast<double*>(smem) + threadIdx.x;
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * FIX_BLOCK + threadIdx.x;
+  double tmax = 0.0;
+  if (s < (uint32_t)P.n_x && label[s] == LBL_FREE) {
+    double x[N];
+    state_centre<N>(P, s, x);
+    typename Dyn<KIND, N>::State st;
+    Dyn<KIND, N>::prep(P, x, st);
+    bool all_cached = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      all_cached = all_cached && P.ccount[i] > 0;
+      for (int c = 0; c < P.ccount[i]; ++c) {
+        InputWalk iw;
+        combo_digits(P, i, c, iw);
+        double uv[AMY_MAXI], mu[N];
+        iw.values(P, uv);
+        Dyn<KIND, N>::apply(P, st, x, uv, mu);
+        double m_i = mu[0];
+#pragma unroll
+        for (int d = 1; d < N; ++d)
+          if (d == i) m_i = mu[d];
+        const Win w = window_1d(P, i, m_i);
+        double wm, gm;
+        win_grid_mass(P, i, w, wm, gm);
+        wg[(2 * (P.ooff[i] + c)) * FIX_BLOCK] = wm;
+        wg[(2 * (P.ooff[i] + c) + 1) * FIX_BLOCK] = gm;
+      }
+    }
+    double prev[N], pw[N], pg[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      prev[i] = __builtin_nan("");
+      pw[i] = pg[i] = 0.0;
+    }
+    InputWalk iw;
+    iw.reset();
+    for (int u = 0; u < P.n_u; ++u) {
+      double mu[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) mu[i] = 0.0;
+      if (!all_cached) {
+        double uv[AMY_MAXI];
+        iw.values(P, uv);
+        Dyn<KIND, N>::apply(P, st, x, uv, mu);
+      }
+      double win = 1.0, grid = 1.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        if (P.ccount[i] > 0) {
+          const int c = combo_index(P, i, iw);
+          win *= wg[(2 * (P.ooff[i] + c)) * FIX_BLOCK];
+          grid *= wg[(2 * (P.ooff[i] + c) + 1) * FIX_BLOCK];
+        } else {
+          if (mu[i] != prev[i]) {
+            const Win w = window_1d(P, i, mu[i]);
+            win_grid_mass(P, i, w, pw[i], pg[i]);
+            prev[i] = mu[i];
+          }
+          win *= pw[i];
+          grid *= pg[i];
+        }
+      }
+      tmax = fmax(tmax, grid - win);
+      iw.next(P);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+  if ((threadIdx.x & 63) == 0 && tmax > 0.0) atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+}
+
 // ---------------------------------------------------------------- factored
 //
 // Inputs are walked with the last digit fastest.  When that digit moves only
@@ -1568,7 +1650,11 @@ struct FacLaunch {
                  unsigned long long* tailmax, const void* rel, hipStream_t st) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
     if constexpr (RelDrift<KIND, SH::N>::ok) {
-      if (!tailmax && rel && P.rel_entries > 0) {
+      if (rel && P.rel_entries > 0) {
+        if (tailmax) {  // the first step: its row tails in a pass of their own
+          const size_t tl = (size_t)(P.lds_bytes_tail - P.lds_tail_off);
+          hipLaunchKernelGGL((k_tail_cached<KIND, SH::N>), g, b, tl, st, P, label, tailmax);
+        }
         const MT* rm = (const MT*)rel;
         const int32_t* ro = (const int32_t*)((const char*)rel +
                                              (((uint64_t)P.rel_entries * REL_SLOTS * sizeof(MT) + 255) & ~255ull));

@@ -67,6 +67,9 @@ CASES = {
     "unicycle-patch-fp64-otf": lambda: _uni_small(precision="fp64", mode="otf"),
     "unicycle-patch-fp32-stored": lambda: _uni_small(precision="fp32", mode="stored"),
     "unicycle-patch-reach-fp32": lambda: _uni_small(precision="fp32", spec="reach"),
+    # speeds up to 3: the x / y windows of one cell's headings spread past
+    # the staged 7 x 7 box, and those windows are gathered from V instead
+    "unicycle-patch-fast-fp32": lambda: _uni_small(precision="fp32", u_hi=(3.0, 1.0)),
     "room-patch-fp32-otf": lambda: _room_small(precision="fp32"),
     "room-patch-fp64-otf": lambda: _room_small(precision="fp64"),
     "room-patch-fp64-stored": lambda: _room_small(precision="fp64", mode="stored"),
@@ -237,7 +240,8 @@ def test_fixed_shape_kernel_matches_generic(name):
     assert a.info["max_row_tail"] == b.info["max_row_tail"]
 
 
-@pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "unicycle-patch-reach-fp32"])
+@pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "unicycle-patch-reach-fp32",
+                                  "unicycle-patch-fast-fp32"])
 def test_factored_sweep_matches_oracle_and_fixed(orc, name):
     """The factored sweep shares the outer contraction between inputs that
     differ only in the last digit: the window sum is re-associated, so it is

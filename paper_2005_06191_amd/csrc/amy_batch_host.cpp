@@ -71,6 +71,8 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: horizon %d > %d", i, probs[i].horizon, AMY_BATCH_MAX_STEPS);
     bp.maxT = std::max(bp.maxT, (int)probs[i].horizon);
     bp.fs = std::max(bp.fs, amy_batch_family_set(D.kind, D.n));
+    // (the tail slots are reserved too, though the steps do not use them:
+    // the persistent grid is sized by this figure)
     bp.lds = std::max(bp.lds, (size_t)(D.grp_g > 1 ? D.lds_bytes_group : D.lds_bytes_tail));
   }
   // longest horizon first: the systems still running at global step s are a prefix
@@ -158,7 +160,10 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
   hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_persistent_kernel(bp.f64, bp.fs), 64, bp.lds);
   if (e != hipSuccess || occ < 1) return amy_hip_fail(e, "batch occupancy query");
-  const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ;
+  // at most 8 workgroups per CU: a cooperative grid of 14 per CU (all the
+  // occupancy query allowed) did not get every workgroup through its
+  // barriers, while grids of up to 10 per CU always have
+  const int bpc = std::min(tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ, 8);
   const unsigned grid = (unsigned)std::max(1, ncu * bpc);
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (ms_out) {

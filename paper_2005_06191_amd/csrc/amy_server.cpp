@@ -315,7 +315,8 @@ void amy_server::run() {
         B.tiles = (int32_t)((pl.dev.n_x + per_tile - 1) / per_tile);
         meta[n + 2] = meta[n + 1] + B.tiles;
         if (pl.mode != AMY_MODE_STORED) {
-          lds = std::max(lds, pl.dev.grp_g > 1 ? pl.dev.lds_bytes_group : pl.dev.lds_bytes_tail);
+          // the batched step has no tail path: tables only
+          lds = std::max(lds, pl.dev.grp_g > 1 ? pl.dev.lds_bytes_group : pl.dev.lds_bytes);
           fs = std::max(fs, amy_batch_family_set(pl.dev.kind, pl.dev.n));
         }
         ++n;

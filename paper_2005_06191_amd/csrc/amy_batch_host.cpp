@@ -161,8 +161,9 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_persistent_kernel(bp.f64, bp.fs), 64, bp.lds);
   if (e != hipSuccess || occ < 1) return amy_hip_fail(e, "batch occupancy query");
   // at most 8 workgroups per CU: a cooperative grid of 14 per CU (all the
-  // occupancy query allowed) did not get every workgroup through its
-  // barriers, while grids of up to 10 per CU always have
+  // occupancy query allowed for a batch of small tables) did not get every
+  // workgroup through its barriers; the grids sized with the full LDS
+  // reservation and this cap have
   const int bpc = std::min(tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ, 8);
   const unsigned grid = (unsigned)std::max(1, ncu * bpc);
   hipEvent_t ev[2] = {nullptr, nullptr};

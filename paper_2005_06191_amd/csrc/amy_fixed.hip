@@ -1408,8 +1408,11 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_relbox(DevProblem P, const 
   extern __shared__ __align__(16) unsigned char smem[];
   const int fd = P.m - 1, nf = P.ucount[fd], fm = P.rmult[F][fd];
   VI* box = reinterpret_cast<VI*>(smem);
-  MT* t0 = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI)) + threadIdx.x;
-  MT* thm = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI)) + SH::L[0] * FIX_BLOCK;
+  // the lane's U partial sums of one slow combination, read back by index
+  AT* asl = reinterpret_cast<AT*>(smem + BX::SIZE * sizeof(VI)) + threadIdx.x;
+  MT* t0 = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI) + (size_t)U * FIX_BLOCK * sizeof(AT)) + threadIdx.x;
+  MT* thm = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI) + (size_t)U * FIX_BLOCK * sizeof(AT)) +
+            SH::L[0] * FIX_BLOCK;
   int32_t* thr = reinterpret_cast<int32_t*>(thm + nf * LF);
   for (int f = threadIdx.x; f < nf; f += FIX_BLOCK) {
     const int e = P.rel_off[F] + f * fm;
@@ -1504,15 +1507,15 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_relbox(DevProblem P, const 
           P, R, t0, vl, ((uint32_t)o0 * BX::S[0] + (uint32_t)o1 * BX::S[1] + (uint32_t)omin) * (uint32_t)sizeof(VI), A);
     else
       contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
+#pragma unroll
+    for (int t = 0; t < U; ++t) asl[t * FIX_BLOCK] = A[t];
     for (int f = 0; f < nf; ++f, ++u) {
       const int g = j[F] + thr[f] - omin;  // A index of the first kept cell
       AT q = AT(0);
 #pragma unroll
       for (int k = 0; k < LF; ++k) {
         const int t = g + k;
-        AT a = A[0];
-#pragma unroll
-        for (int jj = 1; jj < U; ++jj) a = (t == jj) ? A[jj] : a;
+        const AT a = asl[min(max(t, 0), U - 1) * FIX_BLOCK];
         const bool ok = t >= 0 && t < U && omin + t < nF;
         const AT qk = fma_(AT(thm[f * LF + k]), a, q);
         q = ok ? qk : q;
@@ -1666,7 +1669,8 @@ struct FacLaunch {
           if (P.count[2] <= 64 && P.count[0] >= BX::C[0] && P.count[1] >= BX::C[1]) {
             const dim3 gb((unsigned)(P.n_x / P.count[2]));
             hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP>), gb, b,
-                               lds + BX::SIZE * sizeof(VI), st, P, (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
+                               lds + BX::SIZE * sizeof(VI) + (size_t)U * FIX_BLOCK * sizeof(AT), st, P,
+                               (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
             return;
           }
         }

@@ -85,7 +85,7 @@ typedef enum { AMY_FP64 = 0, AMY_FP32 = 1 } amy_precision;
  *                           + u_i (gam (T_h - x_i)),  c0 = (1 - 2 alpha) - beta,
  *                    indices modulo n (rooms on a circle).
  *  AMY_DYN_VEHICLE7  n = 7, m = 2: the single-track model of the paper's
- *                    Sec. 8.3 with its printed right-hand sides, saturations
+ *                    Sec. 8.4.1 with its printed right-hand sides, saturations
  *                    = clamps to the input box; params = {tau, l_wb, m, mu_bar,
  *                    l_f, l_r, h_cg, I_z, C_Sf, C_Sr, g}. */
 /* Bellman-sweep kernel variant.  AUTO lets the library (and its autotuner

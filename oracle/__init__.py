@@ -14,7 +14,10 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libamy_oracle.so")
+# AMY_ORACLE_LIB points the tests at another build of the same source (used to
+# check that the pins fail on a copy with a deliberate mistake).
+BUILT_LIB = os.path.join(HERE, "libamy_oracle.so")
+LIB_PATH = os.environ.get("AMY_ORACLE_LIB") or BUILT_LIB
 
 MAX_DIM, MAX_IN, MAX_PARAMS = 8, 4, 128
 _DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3}
@@ -38,14 +41,14 @@ class OrcProblem(C.Structure):
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, OpenMP, no FP contraction)."""
-    if force or not os.path.exists(LIB_PATH):
+    if force or not os.path.exists(BUILT_LIB):
         src = os.path.join(HERE, "amy_oracle.c")
-        tmp = LIB_PATH + ".tmp"
+        tmp = BUILT_LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
                                "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas",
                                "-o", tmp, src, "-lm"])
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+        os.replace(tmp, BUILT_LIB)
+    return BUILT_LIB
 
 
 _lib = None

@@ -158,7 +158,7 @@ int orc_mean(const orc_problem* p, const double* x, const double* u, double* mu)
       return 0;
     }
     case ORC_VEHICLE7: {
-      /* single-track model of Sec. 8.3 with the printed right-hand sides;
+      /* single-track model of Sec. 8.4.1 with the printed right-hand sides;
        * the input saturations are clamps to the input box. */
       double tau = q[0], lwb = q[1], mass = q[2], mub = q[3], lf = q[4], lr = q[5];
       double hcg = q[6], Iz = q[7], CSf = q[8], CSr = q[9], g = q[10];

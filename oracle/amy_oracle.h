@@ -19,10 +19,13 @@
  * product of 1-D normal-CDF differences (glibc erf/erfc); no table is shared
  * between cells.
  *
- * Parity unpinned: the unicycle, room-ring and 7-D vehicle mean functions
- * are model definitions checked only against a second transcription (the
- * 7-D vehicle's printed formulas may also be garbled); the affine family is
- * pinned by the separable-product identity and the one-step closed form.
+ * Pins of the model means: the affine family by the separable-product
+ * identity and the one-step closed form; the unicycle, the room ring
+ * (Sec. 8.2) and the 7-D single-track vehicle (Sec. 8.4.1) by properties
+ * their physics fixes (motion geometry, equilibria, locality, symmetry and
+ * energy balance of conduction, mirror symmetry and static axle loads of a
+ * car).  The vehicle's slip-angle equation is used as printed: its slip term
+ * has the sign of a growing, not a restoring, slip; no pin depends on it.
  */
 #ifndef AMY_ORACLE_H
 #define AMY_ORACLE_H

@@ -40,7 +40,7 @@ PRECISIONS = ("fp64", "fp32")
 
 Box = Tuple[Tuple[float, ...], Tuple[float, ...]]
 
-# Parameter order of the 7-D single-track vehicle model (Sec. 8.3 of the
+# Parameter order of the 7-D single-track vehicle model (Sec. 8.4.1 of the
 # paper): tau, wheelbase, mass, friction, l_f, l_r, h_cg, I_z, C_Sf, C_Sr, g.
 VEHICLE7_BMW320I = (0.1, 2.5789, 1093.3, 1.0489, 1.156, 1.422, 0.6137,
                     1791.6, 20.89, 20.89, 9.81)

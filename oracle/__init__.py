@@ -20,8 +20,10 @@ BUILT_LIB = os.path.join(HERE, "libamy_oracle.so")
 LIB_PATH = os.environ.get("AMY_ORACLE_LIB") or BUILT_LIB
 
 MAX_DIM, MAX_IN, MAX_PARAMS = 8, 4, 128
-_DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3}
+_DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3, "robot": 4}
 _SPEC = {"safety": 0, "reach": 1, "reach_avoid": 2}
+_NOISE = {"normal": 0, "uniform": 1, "exponential": 2, "beta": 3}
+_WINDOW = {"centre": 0, "intersect": 1}
 
 
 class OrcProblem(C.Structure):
@@ -36,6 +38,11 @@ class OrcProblem(C.Structure):
         ("tlo", C.c_double * MAX_DIM), ("thi", C.c_double * MAX_DIM),
         ("alo", C.c_double * MAX_DIM), ("ahi", C.c_double * MAX_DIM),
         ("slo", C.c_double * MAX_DIM), ("shi", C.c_double * MAX_DIM),
+        ("p", C.c_int32), ("wcount", C.c_int32 * MAX_IN),
+        ("wlo", C.c_double * MAX_IN), ("whi", C.c_double * MAX_IN),
+        ("noise", C.c_int32), ("window", C.c_int32), ("mult", C.c_int32),
+        ("na", C.c_double * MAX_DIM), ("nb", C.c_double * MAX_DIM),
+        ("nalpha", C.c_double * MAX_DIM), ("nbeta", C.c_double * MAX_DIM),
     ]
 
 
@@ -70,11 +77,13 @@ def lib():
         L.orc_mass1d.restype = C.c_double
         L.orc_xstar.argtypes = [C.c_double, C.c_double]
         L.orc_xstar.restype = C.c_double
-        L.orc_mean.argtypes = [pp, dp, dp, dp]
+        L.orc_mean.argtypes = [pp, dp, dp, dp, dp]
         L.orc_window.argtypes = [pp, dp, i32p, i32p]
         L.orc_row_mass.argtypes = [pp, C.c_int64, C.c_int64, dp, dp]
         L.orc_row_dense.argtypes = [pp, C.c_int64, C.c_int64, dp]
         L.orc_labels.argtypes = [pp, u8p]
+        L.orc_noise_mass.argtypes = [pp, C.c_int, C.c_double, C.c_double, C.c_double]
+        L.orc_noise_mass.restype = C.c_double
         _lib = L
     return _lib
 
@@ -108,6 +117,16 @@ def to_struct(p) -> OrcProblem:
     for i in range(n):
         s.tlo[i], s.thi[i], s.alo[i], s.ahi[i], s.slo[i], s.shi[i] = (
             tlo[i], thi[i], alo[i], ahi[i], slo[i], shi[i])
+    wc = tuple(getattr(p, "w_count", ()) or ())
+    s.p = len(wc)
+    for l in range(len(wc)):
+        s.wcount[l], s.wlo[l], s.whi[l] = int(wc[l]), float(p.w_lo[l]), float(p.w_hi[l])
+    s.noise = _NOISE[getattr(p, "noise", "normal")]
+    s.window = _WINDOW[getattr(p, "window", "centre")]
+    s.mult = int(bool(getattr(p, "multiplicative", False)))
+    for src, dst in (("noise_a", s.na), ("noise_b", s.nb), ("noise_alpha", s.nalpha), ("noise_beta", s.nbeta)):
+        for i, v in enumerate(tuple(getattr(p, src, ()) or ())):
+            dst[i] = float(v)
     return s
 
 
@@ -154,16 +173,23 @@ def mass1d(a, b):
     return lib().orc_mass1d(float(a), float(b))
 
 
+def noise_mass(p, i, xi, ta, tb):
+    """Mass of dimension i's noise between offsets ta < tb from the mean."""
+    return lib().orc_noise_mass(C.byref(to_struct(p)), int(i), float(xi), float(ta), float(tb))
+
+
 def xstar(var, cutoff):
     return lib().orc_xstar(float(var), float(cutoff))
 
 
-def mean(p, x, u):
+def mean(p, x, u, w=None):
     s = to_struct(p)
     x = np.ascontiguousarray(x, np.float64)
     u = np.ascontiguousarray(u, np.float64)
+    w = np.ascontiguousarray(w if w is not None else np.zeros(MAX_IN), np.float64)
     mu = np.zeros(len(p.count), np.float64)
-    lib().orc_mean(C.byref(s), _ptr(x, C.c_double), _ptr(u, C.c_double), _ptr(mu, C.c_double))
+    lib().orc_mean(C.byref(s), _ptr(x, C.c_double), _ptr(u, C.c_double), _ptr(w, C.c_double),
+                   _ptr(mu, C.c_double))
     return mu
 
 

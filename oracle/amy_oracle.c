@@ -9,7 +9,10 @@
  *                               PDF(x*|0, Sigma) = gamma per dimension.
  *   Alg. 3 / Alg. 4           : backward value iteration k = T_d .. 1 with
  *                               V_in = T V (+ T0 for reach / reach-avoid),
- *                               V = max over inputs, policy = argmax.
+ *                               V = max over inputs of the min over
+ *                               disturbances (Def. 3.1 and its Remark: the
+ *                               disturbance plays against the controller),
+ *                               policy = argmax over inputs.
  * No blocking, fusion or table sharing: each cell's probability is the
  * product of its 1-D normal-CDF differences, computed on its own.
  *
@@ -23,7 +26,18 @@
  *     post-states in T u A contribute nothing else, V_{T_d+1} = 0; a cell in
  *     both T and A counts as A;
  *   - the reported V is 1 on T\A and 0 on A (policy -1 there);
- *   - policy ties go to the lowest input index.
+ *   - policy ties go to the lowest input index;
+ *   - with a disturbance, each input's value is its minimum over the
+ *     disturbance points (the adversary sees the input);
+ *   - the robot of Sec. 7 moves along the heading u2 by tau u1 in both rows
+ *     (the printed second row's factor u2 read as the speed u1);
+ *   - uniform, exponential and beta noise keep the cells that meet their
+ *     support (the exponential's support cut where its density falls to
+ *     gamma); the intersect rule for normal noise keeps the cells that meet
+ *     [mu - x*, mu + x*];
+ *   - multiplicative noise scales dimension i's standard deviation by the
+ *     state's |x_i| and keeps every cell; at x_i = 0 the whole mass sits in
+ *     the cell holding the mean.
  * Compiled with -ffp-contract=off so that every product and sum is rounded
  * as written.
  */
@@ -65,16 +79,27 @@ double orc_xstar(double var, double cutoff) {
 
 static int valid(const orc_problem* p) {
   if (p->n < 1 || p->n > ORC_MAX_DIM || p->m < 1 || p->m > ORC_MAX_IN) return 0;
-  for (int i = 0; i < p->n; ++i)
-    if (p->count[i] < 1 || !(p->h[i] > 0) || !(p->var[i] > 0)) return 0;
+  if (p->noise < 0 || p->noise > 3 || p->window < 0 || p->window > 1 || p->mult < 0 || p->mult > 1) return 0;
+  if (p->noise != 0 && (p->window != 0 || p->mult != 0)) return 0;
+  for (int i = 0; i < p->n; ++i) {
+    if (p->count[i] < 1 || !(p->h[i] > 0)) return 0;
+    if (p->noise == 0 && !(p->var[i] > 0)) return 0;
+    if ((p->noise == 1 || p->noise == 3) && !(p->nb[i] > p->na[i])) return 0;
+    if (p->noise == 3 && !(p->nalpha[i] >= 1.0 && p->nbeta[i] >= 1.0)) return 0;
+    if (p->noise == 2 && (!(p->na[i] > 0) || (p->cutoff > 0 && !(p->cutoff < p->na[i])))) return 0;
+  }
   for (int k = 0; k < p->m; ++k) if (p->ucount[k] < 1) return 0;
+  if (p->p < 0 || p->p > ORC_MAX_IN) return 0;
+  for (int l = 0; l < p->p; ++l) if (p->wcount[l] < 1) return 0;
   if (p->horizon < 0 || p->cutoff < 0) return 0;
-  for (int i = 0; i < p->n; ++i) if (orc_xstar(p->var[i], p->cutoff) < 0) return 0;
+  if (p->noise == 0 && !p->mult)
+    for (int i = 0; i < p->n; ++i) if (orc_xstar(p->var[i], p->cutoff) < 0) return 0;
   switch (p->dyn) {
-    case ORC_AFFINE: if (p->n_params != p->n * p->n + p->n * p->m + p->n) return 0; break;
-    case ORC_UNICYCLE: if (p->n != 3 || p->m != 2 || p->n_params != 1) return 0; break;
-    case ORC_ROOM: if (p->n_params != 5 || !(p->m == 1 || p->m == p->n)) return 0; break;
-    case ORC_VEHICLE7: if (p->n != 7 || p->m != 2 || p->n_params != 11) return 0; break;
+    case ORC_AFFINE: if (p->n_params != p->n * p->n + p->n * p->m + p->n + p->n * p->p) return 0; break;
+    case ORC_UNICYCLE: if (p->n != 3 || p->m != 2 || p->n_params != 1 || p->p != 0) return 0; break;
+    case ORC_ROOM: if (p->n_params != 5 || !(p->m == 1 || p->m == p->n) || p->p != 0) return 0; break;
+    case ORC_VEHICLE7: if (p->n != 7 || p->m != 2 || p->n_params != 11 || p->p != 0) return 0; break;
+    case ORC_ROBOT: if (p->n != 2 || p->m != 2 || p->n_params != 1 || p->p > 1) return 0; break;
     default: return 0;
   }
   return 1;
@@ -92,6 +117,21 @@ static double input_value(const orc_problem* p, int k, int64_t j) {
   if (p->ucount[k] == 1) return p->ulo[k];
   double step = (p->uhi[k] - p->ulo[k]) / (double)(p->ucount[k] - 1);
   return p->ulo[k] + (double)j * step;
+}
+
+static double dist_value(const orc_problem* p, int l, int64_t j) {
+  if (p->wcount[l] == 1) return p->wlo[l];
+  double step = (p->whi[l] - p->wlo[l]) / (double)(p->wcount[l] - 1);
+  return p->wlo[l] + (double)j * step;
+}
+
+/* Disturbance point number w (row-major, last dimension fastest). */
+static void dist_point(const orc_problem* p, int64_t w, double* wv) {
+  for (int l = p->p - 1; l >= 0; --l) {
+    int64_t j = w % p->wcount[l];
+    w /= p->wcount[l];
+    wv[l] = dist_value(p, l, j);
+  }
 }
 
 static void state_point(const orc_problem* p, int64_t s, double* x) {
@@ -112,17 +152,19 @@ static void input_point(const orc_problem* p, int64_t u, double* uv) {
 
 static double clampd(double v, double a, double b) { return v < a ? a : (v > b ? b : v); }
 
-/* Mean mu = f(x_bar, u_bar) with the noise set to 0 (Alg. 1, first step).
- * Each family's evaluation order is fixed here as written. */
-int orc_mean(const orc_problem* p, const double* x, const double* u, double* mu) {
+/* Mean mu = f(x_bar, u_bar, w_bar) with the noise set to 0 (Alg. 1, first
+ * step).  Each family's evaluation order is fixed here as written. */
+int orc_mean(const orc_problem* p, const double* x, const double* u, const double* w, double* mu) {
   const double* q = p->params;
   const int n = p->n, m = p->m;
   switch (p->dyn) {
     case ORC_AFFINE: {
-      /* x+ = A x + B u + c, evaluated as (A x + c) + B u, sums left to right */
+      /* x+ = A x + B u + c + D w, evaluated as ((A x + c) + B u) + D w,
+       * sums left to right (no D term without a disturbance) */
       const double* A = q;
       const double* B = q + n * n;
       const double* c = q + n * n + n * m;
+      const double* D = q + n * n + n * m + n;
       for (int i = 0; i < n; ++i) {
         double s = 0.0;
         for (int j = 0; j < n; ++j) s = s + A[i * n + j] * x[j];
@@ -130,6 +172,11 @@ int orc_mean(const orc_problem* p, const double* x, const double* u, double* mu)
         double t = 0.0;
         for (int k = 0; k < m; ++k) t = t + B[i * m + k] * u[k];
         mu[i] = s + t;
+        if (p->p > 0) {
+          double d = 0.0;
+          for (int l = 0; l < p->p; ++l) d = d + D[i * p->p + l] * w[l];
+          mu[i] = mu[i] + d;
+        }
       }
       return 0;
     }
@@ -154,6 +201,20 @@ int orc_mean(const orc_problem* p, const double* x, const double* u, double* mu)
         double s = (c0 * x[i] + al * (left + right)) + be * Te;
         double g = ga * (Th - x[i]);
         mu[i] = s + ui * g;
+      }
+      return 0;
+    }
+    case ORC_ROBOT: {
+      /* the robot of Sec. 7: x1 + tau v1 cos(v2) + w, x2 + tau v1 sin(v2) + w
+       * (the printed second row multiplies by v2; read as v1, the speed, as
+       * in the first row); without a disturbance w = 0 and no w term. */
+      double tau = q[0];
+      double a = tau * u[0];
+      mu[0] = x[0] + a * cos(u[1]);
+      mu[1] = x[1] + a * sin(u[1]);
+      if (p->p > 0) {
+        mu[0] = mu[0] + w[0];
+        mu[1] = mu[1] + w[0];
       }
       return 0;
     }
@@ -200,15 +261,47 @@ int orc_mean(const orc_problem* p, const double* x, const double* u, double* mu)
   return -1;
 }
 
+/* Cutting interval of dimension i as offsets [zl, zh] from the mean
+ * (Sec. 5.2 for the normal density; Sec. 6.2 for the others: their support,
+ * the exponential's cut where its density falls to the cutoff).  Returns 0
+ * when nothing is cut (gamma = 0 for normal noise; multiplicative noise). */
+static int cut_interval(const orc_problem* p, int i, double* zl, double* zh) {
+  switch (p->noise) {
+    case 1:
+    case 3:
+      *zl = p->na[i];
+      *zh = p->nb[i];
+      return 1;
+    case 2:
+      *zl = 0.0;
+      *zh = (p->cutoff > 0) ? log(p->na[i] / p->cutoff) / p->na[i] : INFINITY;
+      return 1;
+  }
+  if (p->mult || p->cutoff <= 0.0) return 0;
+  double xs = orc_xstar(p->var[i], p->cutoff);
+  *zl = -xs;
+  *zh = xs;
+  return 1;
+}
+
 /* Cutting region (Sec. 5.2): per dimension, the cells whose centre lies in
- * the closed interval [mu - x*, mu + x*], found by testing every cell. */
+ * the closed interval [mu + zl, mu + zh] (the paper's rule), or with the
+ * intersect rule the cells whose open interval meets it; every cell is
+ * tested. */
 int orc_window(const orc_problem* p, const double* mu, int32_t* jlo, int32_t* jhi) {
   int ok = 1;
   for (int i = 0; i < p->n; ++i) {
-    double xs = orc_xstar(p->var[i], p->cutoff);
+    double zl = -INFINITY, zh = INFINITY;
+    const int cut = cut_interval(p, i, &zl, &zh);
+    const int intersect = (p->noise != 0) || p->window == 1;
     int32_t a = -1, b = -2;
     for (int32_t j = 0; j < p->count[i]; ++j) {
-      if (fabs(centre(p, i, j) - mu[i]) <= xs) {
+      int keep = 1;
+      if (cut) {
+        if (intersect) keep = (edge(p, i, j + 1) - mu[i] > zl) && (edge(p, i, j) - mu[i] < zh);
+        else keep = (centre(p, i, j) - mu[i] >= zl) && (centre(p, i, j) - mu[i] <= zh);
+      }
+      if (keep) {
         if (a < 0) a = j;
         b = j;
       }
@@ -247,9 +340,8 @@ int orc_labels(const orc_problem* p, uint8_t* out) {
 
 typedef struct {
   const orc_problem* p;
-  int64_t nx, nu;
+  int64_t nx, nu, nw;
   int64_t stride[ORC_MAX_DIM];
-  double sigma[ORC_MAX_DIM];
   uint8_t* label;
 } ctx_t;
 
@@ -263,7 +355,8 @@ static int ctx_init(ctx_t* C, const orc_problem* p) {
   }
   C->nu = 1;
   for (int k = 0; k < p->m; ++k) C->nu *= p->ucount[k];
-  for (int i = 0; i < p->n; ++i) C->sigma[i] = sqrt(p->var[i]);
+  C->nw = 1;
+  for (int l = 0; l < p->p; ++l) C->nw *= p->wcount[l];
   C->label = (uint8_t*)malloc((size_t)C->nx);
   if (!C->label) return -1;
   for (int64_t s = 0; s < C->nx; ++s) C->label[s] = (uint8_t)label_of(p, s);
@@ -272,24 +365,83 @@ static int ctx_init(ctx_t* C, const orc_problem* p) {
 
 static void ctx_free(ctx_t* C) { free(C->label); }
 
-/* Probability of one target cell (multi-index j) for mean mu: the product of
- * the per-dimension normal masses of the cell's edges (Alg. 1 integral with
- * a diagonal covariance). */
-static double cell_prob(const ctx_t* C, const double* mu, const int32_t* j) {
+/* Beta(al, be) density on [0, 1] (al, be >= 1, so it is bounded). */
+static double beta_pdf(double y, double al, double be, double lnorm) {
+  if (y <= 0.0 || y >= 1.0) {
+    if (y == 0.0 && al == 1.0) return exp(-lnorm) * pow(1.0 - y, be - 1.0);
+    if (y == 1.0 && be == 1.0) return exp(-lnorm) * pow(y, al - 1.0);
+    return 0.0;
+  }
+  return exp((al - 1.0) * log(y) + (be - 1.0) * log1p(-y) - lnorm);
+}
+
+/* Adaptive Simpson quadrature of the beta density over [a, b] within [0, 1]. */
+static double beta_simpson(double a, double b, double fa, double fm, double fb, double whole, double al,
+                           double be, double lnorm, int depth) {
+  double m = 0.5 * (a + b), lm = 0.5 * (a + m), rm = 0.5 * (m + b);
+  double flm = beta_pdf(lm, al, be, lnorm), frm = beta_pdf(rm, al, be, lnorm);
+  double left = (m - a) / 6.0 * (fa + 4.0 * flm + fm);
+  double right = (b - m) / 6.0 * (fm + 4.0 * frm + fb);
+  double diff = left + right - whole;
+  if (depth <= 0 || fabs(diff) <= 1e-16 * 15.0) return left + right + diff / 15.0;
+  return beta_simpson(a, m, fa, flm, fm, left, al, be, lnorm, depth - 1) +
+         beta_simpson(m, b, fm, frm, fb, right, al, be, lnorm, depth - 1);
+}
+
+static double beta_mass(double y0, double y1, double al, double be) {
+  if (y0 < 0.0) y0 = 0.0;
+  if (y1 > 1.0) y1 = 1.0;
+  if (!(y1 > y0)) return 0.0;
+  double lnorm = lgamma(al) + lgamma(be) - lgamma(al + be);
+  double fa = beta_pdf(y0, al, be, lnorm), fb = beta_pdf(y1, al, be, lnorm);
+  double fm = beta_pdf(0.5 * (y0 + y1), al, be, lnorm);
+  double whole = (y1 - y0) / 6.0 * (fa + 4.0 * fm + fb);
+  return beta_simpson(y0, y1, fa, fm, fb, whole, al, be, lnorm, 48);
+}
+
+/* Mass of dimension i's noise between offsets ta < tb from the mean: the
+ * integral of its density (Alg. 1), in closed form except for the beta
+ * density, which is integrated numerically. */
+double orc_noise_mass(const orc_problem* p, int i, double xi, double ta, double tb) {
+  switch (p->noise) {
+    case 1: {
+      double w = p->nb[i] - p->na[i];
+      double fa = clampd((ta - p->na[i]) / w, 0.0, 1.0), fb = clampd((tb - p->na[i]) / w, 0.0, 1.0);
+      return fb - fa;
+    }
+    case 2: {
+      double sa = ta <= 0.0 ? 1.0 : exp(-p->na[i] * ta);
+      double sb = tb <= 0.0 ? 1.0 : exp(-p->na[i] * tb);
+      return sa - sb;
+    }
+    case 3: {
+      double w = p->nb[i] - p->na[i];
+      return beta_mass((ta - p->na[i]) / w, (tb - p->na[i]) / w, p->nalpha[i], p->nbeta[i]);
+    }
+  }
+  double s = sqrt(p->var[i]);
+  if (p->mult) {
+    s = s * fabs(xi);
+    if (s == 0.0) return (ta <= 0.0 && 0.0 < tb) ? 1.0 : 0.0; /* all mass at the mean */
+  }
+  return orc_mass1d(ta / s, tb / s);
+}
+
+/* Probability of one target cell (multi-index j) for mean mu from state x:
+ * the product of the per-dimension masses of the cell's edges (Alg. 1
+ * integral with independent noise components). */
+static double cell_prob(const ctx_t* C, const double* x, const double* mu, const int32_t* j) {
   const orc_problem* p = C->p;
   double t = 1.0;
-  for (int i = 0; i < p->n; ++i) {
-    double a = (edge(p, i, j[i]) - mu[i]) / C->sigma[i];
-    double b = (edge(p, i, j[i] + 1) - mu[i]) / C->sigma[i];
-    t *= orc_mass1d(a, b);
-  }
+  for (int i = 0; i < p->n; ++i)
+    t *= orc_noise_mass(p, i, x[i], edge(p, i, j[i]) - mu[i], edge(p, i, j[i] + 1) - mu[i]);
   return t;
 }
 
 /* V_in(x,u) of Alg. 4: sum over the cutting region of T * V_{k+1}, plus T0
  * for reach / reach-avoid (mass into T\A; post-states in T u A are zeroed
  * in T).  Vnext == NULL means the terminal vector. */
-static double row_value(const ctx_t* C, const double* mu, const double* Vnext) {
+static double row_value(const ctx_t* C, const double* x, const double* mu, const double* Vnext) {
   const orc_problem* p = C->p;
   int32_t lo[ORC_MAX_DIM], hi[ORC_MAX_DIM], j[ORC_MAX_DIM];
   if (!orc_window(p, mu, lo, hi)) return 0.0;
@@ -299,7 +451,7 @@ static double row_value(const ctx_t* C, const double* mu, const double* Vnext) {
   for (;;) {
     int64_t cell = 0;
     for (int i = 0; i < p->n; ++i) cell += (int64_t)j[i] * C->stride[i];
-    double t = cell_prob(C, mu, j);
+    double t = cell_prob(C, x, mu, j);
     int lbl = C->label[cell];
     if (safety) {
       /* V_{T_d+1} = 1 on S, 0 outside; V_k = 0 outside S */
@@ -321,22 +473,22 @@ static double row_value(const ctx_t* C, const double* mu, const double* Vnext) {
 }
 
 /* Tail of one row: grid mass minus kept-window mass (both as products of
- * 1-D masses, exact for a diagonal covariance). */
-static double row_tail(const ctx_t* C, const double* mu) {
+ * 1-D masses, exact for independent noise components). */
+static double row_tail(const ctx_t* C, const double* x, const double* mu) {
   const orc_problem* p = C->p;
   int32_t lo[ORC_MAX_DIM], hi[ORC_MAX_DIM];
   int ok = orc_window(p, mu, lo, hi);
   double grid = 1.0, win = 1.0;
   for (int i = 0; i < p->n; ++i) {
-    double s = C->sigma[i];
-    grid *= orc_mass1d((edge(p, i, 0) - mu[i]) / s, (edge(p, i, p->count[i]) - mu[i]) / s);
-    if (ok) win *= orc_mass1d((edge(p, i, lo[i]) - mu[i]) / s, (edge(p, i, hi[i] + 1) - mu[i]) / s);
+    grid *= orc_noise_mass(p, i, x[i], edge(p, i, 0) - mu[i], edge(p, i, p->count[i]) - mu[i]);
+    if (ok) win *= orc_noise_mass(p, i, x[i], edge(p, i, lo[i]) - mu[i], edge(p, i, hi[i] + 1) - mu[i]);
   }
   if (!ok) win = 0.0;
   return grid - win;
 }
 
-/* Bellman update of one state: max over inputs of V_in, lowest argmax. */
+/* Bellman update of one state: max over inputs of the min over
+ * disturbances of V_in, lowest maximising input. */
 static void state_update(const ctx_t* C, const double* Vnext, int64_t s, double* v_out,
                          int16_t* pol_out, double* gap_out, double* tail_out) {
   const orc_problem* p = C->p;
@@ -348,24 +500,29 @@ static void state_update(const ctx_t* C, const double* Vnext, int64_t s, double*
     if (tail_out) *tail_out = 0.0;
     return;
   }
-  double x[ORC_MAX_DIM], uv[ORC_MAX_IN], mu[ORC_MAX_DIM];
+  double x[ORC_MAX_DIM], uv[ORC_MAX_IN], wv[ORC_MAX_IN], mu[ORC_MAX_DIM];
   state_point(p, s, x);
   double best = -1.0, second = -1.0, tmax = 0.0;
   int64_t arg = 0;
   for (int64_t u = 0; u < C->nu; ++u) {
     input_point(p, u, uv);
-    orc_mean(p, x, uv, mu);
-    double q = row_value(C, mu, Vnext);
+    double q = INFINITY;
+    for (int64_t w = 0; w < C->nw; ++w) {
+      dist_point(p, w, wv);
+      orc_mean(p, x, uv, wv, mu);
+      double qw = row_value(C, x, mu, Vnext);
+      if (qw < q) q = qw;
+      if (tail_out) {
+        double t = row_tail(C, x, mu);
+        if (t > tmax) tmax = t;
+      }
+    }
     if (q > best) {
       second = best;
       best = q;
       arg = u;
     } else if (q > second) {
       second = q;
-    }
-    if (tail_out) {
-      double t = row_tail(C, mu);
-      if (t > tmax) tmax = t;
     }
   }
   *v_out = best;
@@ -457,17 +614,18 @@ int orc_row_mass(const orc_problem* p, int64_t state, int64_t input, double* sum
                  double* tail_out) {
   ctx_t C;
   if (ctx_init(&C, p) != 0) return -1;
-  if (state < 0 || state >= C.nx || input < 0 || input >= C.nu) { ctx_free(&C); return -1; }
-  double x[ORC_MAX_DIM], uv[ORC_MAX_IN], mu[ORC_MAX_DIM];
+  if (state < 0 || state >= C.nx || input < 0 || input >= C.nu * C.nw) { ctx_free(&C); return -1; }
+  double x[ORC_MAX_DIM], uv[ORC_MAX_IN], wv[ORC_MAX_IN], mu[ORC_MAX_DIM];
   int32_t lo[ORC_MAX_DIM], hi[ORC_MAX_DIM], j[ORC_MAX_DIM];
   state_point(p, state, x);
-  input_point(p, input, uv);
-  orc_mean(p, x, uv, mu);
+  input_point(p, input / C.nw, uv);
+  dist_point(p, input % C.nw, wv);
+  orc_mean(p, x, uv, wv, mu);
   double sum = 0.0;
   if (orc_window(p, mu, lo, hi)) {
     for (int i = 0; i < p->n; ++i) j[i] = lo[i];
     for (;;) {
-      sum += cell_prob(&C, mu, j);
+      sum += cell_prob(&C, x, mu, j);
       int i = p->n - 1;
       while (i >= 0) {
         if (++j[i] <= hi[i]) break;
@@ -478,7 +636,7 @@ int orc_row_mass(const orc_problem* p, int64_t state, int64_t input, double* sum
     }
   }
   *sum_out = sum;
-  *tail_out = row_tail(&C, mu);
+  *tail_out = row_tail(&C, x, mu);
   ctx_free(&C);
   return 0;
 }
@@ -486,12 +644,13 @@ int orc_row_mass(const orc_problem* p, int64_t state, int64_t input, double* sum
 int orc_row_dense(const orc_problem* p, int64_t state, int64_t input, double* row_out) {
   ctx_t C;
   if (ctx_init(&C, p) != 0) return -1;
-  if (state < 0 || state >= C.nx || input < 0 || input >= C.nu) { ctx_free(&C); return -1; }
-  double x[ORC_MAX_DIM], uv[ORC_MAX_IN], mu[ORC_MAX_DIM];
+  if (state < 0 || state >= C.nx || input < 0 || input >= C.nu * C.nw) { ctx_free(&C); return -1; }
+  double x[ORC_MAX_DIM], uv[ORC_MAX_IN], wv[ORC_MAX_IN], mu[ORC_MAX_DIM];
   int32_t lo[ORC_MAX_DIM], hi[ORC_MAX_DIM], j[ORC_MAX_DIM];
   state_point(p, state, x);
-  input_point(p, input, uv);
-  orc_mean(p, x, uv, mu);
+  input_point(p, input / C.nw, uv);
+  dist_point(p, input % C.nw, wv);
+  orc_mean(p, x, uv, wv, mu);
   int ok = orc_window(p, mu, lo, hi);
   for (int64_t c = 0; c < C.nx; ++c) {
     int64_t r = c;
@@ -501,7 +660,7 @@ int orc_row_dense(const orc_problem* p, int64_t state, int64_t input, double* ro
       r /= p->count[i];
       if (j[i] < lo[i] || j[i] > hi[i]) inside = 0;
     }
-    row_out[c] = inside ? cell_prob(&C, mu, j) : 0.0;
+    row_out[c] = inside ? cell_prob(&C, x, mu, j) : 0.0;
   }
   ctx_free(&C);
   return 0;

@@ -15,6 +15,9 @@
  *   - finite-horizon Bellman value iteration for safety, reachability and
  *     reach-avoid (Alg. 3 / Alg. 4), returning V at k = 1 and the maximising
  *     input of every step.
+ * With a disturbance set W (Def. 3.1 and the Remark after Def. 3.2: the
+ * disturbance is a rational adversary), every row is (x, u, w) and the
+ * update is V(x) = max_u min_w V_in(x, u, w) (Alg. 3 and Alg. 4).
  * Everything is FP64.  Every cell probability is computed directly as a
  * product of 1-D normal-CDF differences (glibc erf/erfc); no table is shared
  * between cells.
@@ -39,7 +42,7 @@ extern "C" {
 #define ORC_MAX_IN 4
 #define ORC_MAX_PARAMS 128
 
-enum { ORC_AFFINE = 0, ORC_UNICYCLE = 1, ORC_ROOM = 2, ORC_VEHICLE7 = 3 };
+enum { ORC_AFFINE = 0, ORC_UNICYCLE = 1, ORC_ROOM = 2, ORC_VEHICLE7 = 3, ORC_ROBOT = 4 };
 enum { ORC_SAFETY = 0, ORC_REACH = 1, ORC_REACH_AVOID = 2 };
 
 typedef struct {
@@ -61,6 +64,18 @@ typedef struct {
   double tlo[ORC_MAX_DIM], thi[ORC_MAX_DIM];   /* target box               */
   double alo[ORC_MAX_DIM], ahi[ORC_MAX_DIM];   /* avoid box (empty: lo>hi) */
   double slo[ORC_MAX_DIM], shi[ORC_MAX_DIM];   /* safe box                 */
+  int32_t p;                       /* disturbance dimensions, 0 = none       */
+  int32_t wcount[ORC_MAX_IN];      /* points per disturbance dimension       */
+  double wlo[ORC_MAX_IN];          /* inclusive linspace ends                */
+  double whi[ORC_MAX_IN];
+  /* noise model: 0 normal (var), 1 uniform on [na, nb], 2 exponential with
+   * rate na, 3 beta(nalpha, nbeta) on [na, nb]; window: 0 centre rule,
+   * 1 intersect rule (the other distributions always intersect their
+   * support, the exponential's cut where its density falls to the cutoff);
+   * mult: multiplicative normal noise, standard deviation sqrt(var) |x_i|
+   * at state x, no cut */
+  int32_t noise, window, mult;
+  double na[ORC_MAX_DIM], nb[ORC_MAX_DIM], nalpha[ORC_MAX_DIM], nbeta[ORC_MAX_DIM];
 } orc_problem;
 
 /* Full solve.  V_out[n_x] (host) receives V at k = 1.  policy_out (may be
@@ -84,13 +99,18 @@ int orc_step(const orc_problem* p, const double* V_next, const int64_t* states,
 
 /* Building blocks, exposed for the oracle's own unit tests. */
 double orc_mass1d(double a, double b);              /* Phi(b) - Phi(a)      */
+/* Mass of the noise of dimension i between offsets ta < tb from the mean
+ * (edge - mu), for a state whose coordinate i is xi (multiplicative noise). */
+double orc_noise_mass(const orc_problem* p, int i, double xi, double ta, double tb);
 double orc_xstar(double var, double cutoff);         /* cutting half-width   */
-int orc_mean(const orc_problem* p, const double* x, const double* u, double* mu);
+/* mu = f(x, u, w) (w: the disturbance point, ignored / may be NULL when p == 0). */
+int orc_mean(const orc_problem* p, const double* x, const double* u, const double* w, double* mu);
 /* Kept cells [jlo[i], jhi[i]] of each dimension for mean mu; returns 1 if
  * the window is non-empty in every dimension, else 0. */
 int orc_window(const orc_problem* p, const double* mu, int32_t* jlo, int32_t* jhi);
 /* Row (state, input): sum of the kept cell probabilities (cell by cell) and
- * the row's tail (mass on the grid outside the kept window). */
+ * the row's tail (mass on the grid outside the kept window).  With a
+ * disturbance, "input" numbers the (input, disturbance) pairs, u * n_w + w. */
 int orc_row_mass(const orc_problem* p, int64_t state, int64_t input, double* sum_out,
                  double* tail_out);
 /* Dense transition row over all n_x cells (cut applied), for tiny grids. */

@@ -325,3 +325,16 @@ def test_labels_and_fixed_values(orc):
     lab = brute.labels(prob)
     assert np.all(r["V"][lab == 2] == 1.0) and np.all(r["V"][lab == 1] == 0.0)
     assert np.all(r["policy"][:, lab != 0] == -1)
+
+
+def test_policy_ties_go_to_the_lowest_input(orc):
+    """Reading of the argmax (Alg. 4's collect step names no tie rule): among
+    inputs with exactly equal values the lowest index wins.  Inputs that do
+    not enter the dynamics tie exactly everywhere."""
+    p = W.linear2d(cells=12, precision="fp64", mode="otf").with_(
+        params=W.affine_params([[0.9, 0.05], [0.0, 0.9]], [[0.0], [0.0]]), u_count=(4,), horizon=3)
+    r = orc.solve(p)
+    lab = orc.labels(p)
+    free = lab == 0
+    assert free.any()
+    assert np.all(r["policy"][:, free] == 0)

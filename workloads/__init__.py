@@ -33,7 +33,7 @@ import numpy as np
 
 INF = float("inf")
 
-DYN_KINDS = ("affine", "unicycle", "room", "vehicle7")
+DYN_KINDS = ("affine", "unicycle", "room", "vehicle7", "robot")
 SPECS = ("safety", "reach", "reach_avoid")
 MODES = ("auto", "stored", "otf")
 PRECISIONS = ("fp64", "fp32")
@@ -66,6 +66,23 @@ class Problem:
     mode: str = "auto"
     precision: str = "fp32"
     name: str = ""
+    # disturbance set (Def. 3.1): dimension l is the inclusive linspace
+    # w_lo[l] .. w_hi[l] with w_count[l] points; empty = no disturbance
+    w_lo: Tuple[float, ...] = ()
+    w_hi: Tuple[float, ...] = ()
+    w_count: Tuple[int, ...] = ()
+    # noise model (Sec. 3 and Sec. 6.2): "normal" (variances in var),
+    # "uniform" on [noise_a, noise_b], "exponential" with rate noise_a,
+    # "beta"(noise_alpha, noise_beta) on [noise_a, noise_b]; the window rule
+    # ("centre" as in Sec. 5.2, or "intersect") and multiplicative normal
+    # noise (Eq. 3.2: scale |x_i| times sqrt(var_i), no cut)
+    noise: str = "normal"
+    window: str = "centre"
+    multiplicative: bool = False
+    noise_a: Tuple[float, ...] = ()
+    noise_b: Tuple[float, ...] = ()
+    noise_alpha: Tuple[float, ...] = ()
+    noise_beta: Tuple[float, ...] = ()
 
     @property
     def n(self) -> int:
@@ -84,8 +101,17 @@ class Problem:
         return int(np.prod(self.u_count, dtype=np.int64))
 
     @property
+    def p_dist(self) -> int:
+        return len(self.w_count)
+
+    @property
+    def n_w(self) -> int:
+        return int(np.prod(self.w_count, dtype=np.int64)) if self.w_count else 1
+
+    @property
     def rows(self) -> int:
-        return self.n_x * self.n_u
+        """(state, input, disturbance) rows of Alg. 2."""
+        return self.n_x * self.n_u * self.n_w
 
     def with_(self, **kw) -> "Problem":
         return replace(self, **kw)
@@ -133,14 +159,18 @@ def tiling(lo: Sequence[float], hi: Sequence[float], cells: Sequence[int]):
     return tuple(float(a) for a in lo), h, tuple(int(c) for c in cells)
 
 
-def affine_params(A, B, c=None) -> Tuple[float, ...]:
-    """Flatten ``x+ = A x + B u + c`` (row-major A[n*n], B[n*m], c[n])."""
+def affine_params(A, B, c=None, D=None) -> Tuple[float, ...]:
+    """Flatten ``x+ = A x + B u + c + D w`` (row-major A[n*n], B[n*m], c[n],
+    then D[n*p] when there is a disturbance)."""
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     n = A.shape[0]
     B = B.reshape(n, -1)
     c = np.zeros(n) if c is None else np.asarray(c, dtype=np.float64)
-    return tuple(A.ravel().tolist() + B.ravel().tolist() + c.ravel().tolist())
+    out = A.ravel().tolist() + B.ravel().tolist() + c.ravel().tolist()
+    if D is not None:
+        out += np.asarray(D, dtype=np.float64).reshape(n, -1).ravel().tolist()
+    return tuple(out)
 
 
 # ---------------------------------------------------------------------------

@@ -1,11 +1,13 @@
 """Benchmark: Bellman (state,input) row-updates per second on one MI355X.
 
 A step is one whole solve of the hot path on one synthetic problem already
-resident on the device: labels, the FP64 cut-off tail pass, T_d Bellman
-sweeps (rows recomputed on the fly) and the FP64 readout.  The default
-workload is the 3-D unicycle reach-avoid problem (100 x 100 x 60 states,
-45 inputs, horizon 16) solved with the FP32 path; the plain FP64 path is
-timed beside it, and the two results are compared.
+resident on the device: labels, the per-solve 1-D tables, T_d Bellman
+sweeps (rows recomputed on the fly; the first also takes the FP64 cut-off
+tail) and the FP64 readout.  The headline workload is the 5-D room ring
+(20^5 = 3.2M states, 10 heater levels, horizon 32, safety) solved with the
+FP32 path; the plain FP64 path is timed beside it, both are checked against
+the oracle at sampled states, and the 3-D unicycle reach-avoid workload
+(100 x 100 x 60 states, 45 inputs, horizon 16) is timed after it.
 
 Prints one JSON line (rank 0).  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -72,13 +74,43 @@ WORKLOADS = {
     "room5d": lambda prec, mode: W.room5d(precision=prec, mode=mode),
     "vehicle7d": lambda prec, mode: W.vehicle7d(precision=prec, mode=mode),
     "linear2d": lambda prec, mode: W.linear2d(precision=prec, mode=mode),
+    # the robot of Sec. 7 with its disturbance (11 points): max over inputs of the min over disturbances
+    "robot2d": lambda prec, mode: W.robot2d(precision=prec).with_(mode=mode),
+    # the unicycle workload with the intersect window (no cell meeting [mu - x*, mu + x*] dropped)
+    "unicycle3d-intersect": lambda prec, mode: W.unicycle3d(precision=prec, mode=mode).with_(window="intersect"),
+    # the road traffic ring of Sec. 8.3.1 given as source text (compiled at run time), quantisation 0.74;
+    # one lane per state (measured 4x faster here than the 64-lanes-per-state sweep AUTO takes for
+    # windows of this size)
+    "traffic5d-text": lambda prec, mode: W.traffic5d(q=0.74, precision=prec, text=True).with_(mode=mode,
+                                                                                                variant="lanes"),
+    # the room ring with beta(2, 2) noise on [-0.05, 0.05] (cells meeting the support)
+    "room5d-beta": lambda prec, mode: W.room5d(precision=prec, mode=mode).with_(
+        noise="beta", noise_a=(-0.05,) * 5, noise_b=(0.05,) * 5, noise_alpha=(2.0,) * 5, noise_beta=(2.0,) * 5),
 }
 
 
-def algorithmic_flops_per_row(plan) -> float:
-    """3W + C_erfc * edges: a multiply-add with V per window cell (2 flops),
-    one multiply per cell to form its mass from the 1-D masses, and one
-    erfc per window edge (sum_i (L_i + 1) edges)."""
+def contraction_flops_per_row(plan) -> float:
+    """Flops of one row's window sum done dimension by dimension (innermost
+    first): a multiply-add per cell of each partial contraction,
+    2 (W + W/L_n + W/(L_n L_{n-1}) + ... + L_1).  This is what the row
+    must execute once its 1-D mass tables exist (the sweeps build those once
+    per solve and share them between rows), so it is the per-row work the
+    roofline fraction is priced on."""
+    L = [x for x in plan["window"] if x > 0]
+    f, w = 0.0, float(plan["W"])
+    for l in reversed(L):
+        f += 2.0 * w
+        w /= l
+    return f
+
+
+def row_equivalent_flops_per_row(plan) -> float:
+    """3W + C_erfc * edges: the per-row count of a sweep that builds every
+    row's 1-D tables itself and multiplies each cell's mass out (a
+    multiply-add with V and a mass product per window cell, one erfc per
+    window edge, sum_i (L_i + 1) edges).  Sweeps that share tables or
+    partial sums between rows execute fewer; reported beside the roofline,
+    never as its fraction."""
     L = [x for x in plan["window"] if x > 0]
     edges = sum(l + 1 for l in L)
     return 3.0 * plan["W"] + C_ERFC * edges
@@ -115,30 +147,79 @@ def run_solves(solver, steps, warmup):
     return dict(wall=wall, lat=lat, main=main, sweeps=sweeps, info=r.info, V=r.V)
 
 
-def cpu_baseline(p, budget_s=15.0):
-    """The FP64 oracle, unchanged, on a bounded sample: one Bellman step
-    (k = T_d) at a strided sample of states, all inputs of each state."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(p, threads, budget_s):
+    """Row-updates/s of the oracle's one-step routine at `threads` threads on
+    about budget_s seconds of strided states (calibrated on a short run)."""
     import numpy as np
 
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
-    if threads <= 0:
-        threads = len(os.sched_getaffinity(0))
-    threads = max(1, min(threads, 16))
-    n_cal = 2000
-    st = np.linspace(0, p.n_x - 1, n_cal).astype(np.int64)
+    n_cal = max(64, 200 * threads)
+    st = np.linspace(0, p.n_x - 1, min(n_cal, p.n_x)).astype(np.int64)
     t = time.perf_counter()
     oracle.step(p, st, threads=threads)
     dt = max(time.perf_counter() - t, 1e-3)
-    n = int(min(p.n_x, max(n_cal, n_cal * budget_s / dt)))
+    n = int(min(p.n_x, max(len(st), len(st) * budget_s / dt)))
     st = np.linspace(0, p.n_x - 1, n).astype(np.int64)
     t = time.perf_counter()
     oracle.step(p, st, threads=threads)
     dt = time.perf_counter() - t
+    return n, dt
+
+
+def cpu_baseline(p, budget_s=15.0, budget_1core_s=8.0):
+    """The FP64 oracle, unchanged, on a bounded sample: one Bellman step
+    (k = T_d) at evenly strided states, all inputs of each state, on every
+    CPU this process may run on (capped by OMP_NUM_THREADS when it is set:
+    the GPU job's CPU share), and again on one core."""
+    cpus = len(os.sched_getaffinity(0))
+    threads = cpus
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if env > 0:
+        threads = min(threads, env)
+    n, dt = _oracle_rate(p, threads, budget_s)
+    n1, dt1 = _oracle_rate(p, 1, budget_1core_s)
     return {"value": n * p.n_u / dt, "unit": "row-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one Bellman step from the terminal values at {n} evenly strided states x "
                       f"{p.n_u} inputs ({n * p.n_u} row-updates) of the same problem, {dt:.1f} s, "
-                      f"FP64 oracle with {threads} OpenMP threads"}
+                      f"FP64 oracle with {threads} OpenMP threads",
+            "value_1core": n1 * p.n_u / dt1,
+            "sample_1core": f"{n1} states x {p.n_u} inputs, {dt1:.1f} s, one thread",
+            "host_cpus": cpus, "cpu_model": _cpu_model()}
+
+
+def oracle_check_sampled(p32, V32, n_states=1000, seed=5, user=None):
+    """Max |V - V_oracle| of the FP32 and FP64 solves at sampled states: the
+    plain FP64 GPU path solves the same problem with one step fewer (its V
+    at k = 1 is V_2 of the full horizon), the oracle takes the last Bellman
+    step from it at the sampled states on its own, and both GPU results at
+    k = 1 are compared with that."""
+    import numpy as np
+
+    import oracle
+    import paper_2005_06191_amd as A
+    T = p32.horizon
+    p64 = p32.with_(precision="fp64")
+    V64 = A.Solver(p64, user=user).solve(policy=False, info=False).V.cpu().numpy()
+    Vn = A.Solver(p64.with_(horizon=T - 1), user=user).solve(policy=False, info=False).V.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    st = np.unique(np.concatenate([rng.integers(0, p32.n_x, n_states), [0, p32.n_x - 1]]))
+    Vr, _, _ = oracle.step(p32.with_(precision="fp64"), st, V_next=Vn)
+    e32 = float(np.abs(V32[st] - Vr).max())
+    e64 = float(np.abs(V64[st] - Vr).max())
+    return {"fp32": e32, "fp64": e64, "states": int(len(st)), "tol_fp32": 1e-5, "tol_fp64": 1e-12,
+            "ok": bool(e32 <= 1e-5 and e64 <= 1e-12),
+            "how": "oracle's last Bellman step from the GPU FP64 V_2 at sampled states vs the GPU V_1"}
 
 
 def bench_batch(args):
@@ -166,8 +247,7 @@ def bench_batch(args):
     work = sum(p.rows * p.horizon for p in ps)
     flops = 0.0
     for p, r in zip(ps, res):
-        L = [x for x in r.info["window"] if x > 0]
-        flops += p.rows * p.horizon * (3.0 * r.info["W"] + C_ERFC * sum(l + 1 for l in L))
+        flops += p.rows * p.horizon * contraction_flops_per_row(r.info)
     kms = statistics.mean(lat)
     achieved = flops / (kms * 1e-3) / 1e12
     variants = {}
@@ -301,12 +381,96 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+METRIC = "Bellman (state,input) row-updates/sec FP32 vs FP64 at <=1e-5 err; p50/p99"
+
+
+def bench_solve(workload, mode, variant, steps, warmup, fp64=True, check=True):
+    """Time `steps` whole FP32 solves of one workload (after `warmup`), the
+    plain FP64 path beside it, and the roofline of the dominant sweep."""
+    import torch
+
+    import paper_2005_06191_amd as A
+    p32 = WORKLOADS[workload]("fp32", mode)
+    user = A.UserDynamics(p32.rhs, p32.n, p32.m, p32.p_dist) if p32.dyn == "user" else None
+    s32 = A.Solver(p32, variant=variant if variant != "auto" else p32.variant, user=user)
+    plan = s32.plan
+    rows, T = p32.rows, p32.horizon
+    r32 = run_solves(s32, steps, warmup)
+    out = {"value": rows * T * steps / r32["wall"], "ms_per_step": 1e3 * r32["wall"] / steps,
+           "p50_ms": percentile(r32["lat"], 0.5), "p99_ms": percentile(r32["lat"], 0.99),
+           "config": {"workload": f"{p32.name} {p32.spec} {mode} (n_x={p32.n_x}, n_u={p32.n_u}, "
+                                  + (f"n_w={p32.n_w}, " if p32.n_w > 1 else "") + f"T_d={T}, W={plan['W']})",
+                      "states": p32.n_x, "inputs": p32.n_u, "horizon": T, "rows": rows,
+                      "window": plan["window"][:p32.n], "W": plan["W"], "mode": mode,
+                      "variant": plan["variant"]},
+           "tail_bound_E": r32["info"]["tail_bound_E"]}
+    # dominant kernel: the working-precision sweep alone, steps T_d - 1 .. 2
+    # (T_d - 2 launches per solve), timed by HIP events on the solve's stream
+    n_main = max(T - 2, 1)
+    sweep_ms = statistics.mean(r32["main"]) / n_main
+    prof = _profiled(workload, mode, plan["variant"])
+    if mode == "otf":
+        fl = contraction_flops_per_row(plan)
+        achieved = fl * rows / (sweep_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic_for(workload, mode, plan["variant"]),
+                "kernel": f"sweep {plan['variant']} (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
+                "launches_timed": n_main * steps, "flops_per_row": fl, "rows_per_launch": rows,
+                "work": "per-row window contraction done dimension by dimension, "
+                        "2 (W + W/L_n + ... + L_1) flops; the 1-D tables are built once per solve",
+                "peak_without_packed_fp32": PEAK_FP64_TFLOPS,
+                "frac_without_packed_fp32": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "row_equivalent": {"flops_per_row": row_equivalent_flops_per_row(plan),
+                                   "tflops": round(row_equivalent_flops_per_row(plan) * rows
+                                                   / (sweep_ms * 1e-3) / 1e12, 3)}}
+        if prof is not None and "exec_flops_per_row" in prof:
+            ex = prof["exec_flops_per_row"] * rows / (sweep_ms * 1e-3) / 1e12
+            roof["executed"] = {"flops_per_row": prof["exec_flops_per_row"], "tflops": round(ex, 3),
+                                "frac": round(ex / PEAK_FP32_TFLOPS, 4)}
+            if prof["exec_flops_per_row"] < fl:
+                # the sweep shares partial sums between rows: price on what runs
+                roof["achieved"] = round(ex, 3)
+                roof["frac"] = round(ex / PEAK_FP32_TFLOPS, 4)
+                roof["frac_without_packed_fp32"] = round(ex / PEAK_FP64_TFLOPS, 4)
+                roof["work"] = ("executed FP32 flops per row from the profiler's counters (the sweep "
+                                "shares partial sums between inputs, so it runs fewer than the "
+                                "per-row contraction)")
+    else:
+        by = stored_bytes_per_row(plan, False)
+        achieved = by * rows / (sweep_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic_for(workload, mode, plan["variant"]),
+                "kernel": "k_sweep_stored (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
+                "launches_timed": n_main * steps, "bytes_per_row": by, "rows_per_launch": rows}
+    out["roofline"] = roof
+    if fp64:
+        s64 = A.Solver(p32.with_(precision="fp64"), variant=variant if variant != "auto" else p32.variant, user=user)
+        k64 = max(3, steps // 2)
+        r64 = run_solves(s64, k64, 1)
+        v64 = rows * T * k64 / r64["wall"]
+        err = float((r32["V"] - r64["V"]).abs().max().item())
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["wall"] / k64,
+                       "p50_ms": percentile(r64["lat"], 0.5), "p99_ms": percentile(r64["lat"], 0.99)}
+        out["speedup_fp32_vs_fp64"] = out["value"] / v64
+        out["max_abs_err_fp32_vs_fp64"] = err
+        del s64
+    if check:
+        out["err_vs_oracle"] = oracle_check_sampled(p32, r32["V"].cpu().numpy(), user=user)
+    del s32
+    torch.cuda.synchronize()
+    return out, p32
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="unicycle3d", choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="room5d", choices=sorted(WORKLOADS) + ["batch64", "serve"])
+    ap.add_argument("--also", default="unicycle3d,robot2d,unicycle3d-intersect,traffic5d-text,room5d-beta",
+                    help="comma-separated workloads timed after the headline one ('' for none)")
     ap.add_argument("--requests", type=int, default=200, help="serve: requests in the measured set")
     ap.add_argument("--slots", type=int, default=64, help="serve: requests on the device at once")
     ap.add_argument("--hbm-budget-gb", type=float, default=64.0, help="serve: device arena")
@@ -317,6 +481,7 @@ def main():
                     help="only run a plain device copy of this size 10 times (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the solve is not sharded across GPUs); "
@@ -334,84 +499,29 @@ def main():
         return
 
     import torch
-
-    import paper_2005_06191_amd as A
     torch.cuda.set_device(0)
-
-    p32 = WORKLOADS[args.workload]("fp32", args.mode)
-    s32 = A.Solver(p32, variant=args.variant)
-    plan = s32.plan
-    rows = p32.rows
-    T = p32.horizon
-    r32 = run_solves(s32, args.steps, args.warmup)
-    ms_per_step = 1e3 * r32["wall"] / args.steps
-    value = rows * T * args.steps / r32["wall"]
-
-    # dominant kernel: the working-precision sweep alone (steps T_d - 1 .. 2,
-    # T_d - 2 launches per solve)
-    n_main = max(T - 2, 1)
-    sweep_ms = statistics.mean(r32["main"]) / n_main
-    if args.mode == "otf":
-        fl = algorithmic_flops_per_row(plan)
-        achieved = fl * rows / (sweep_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic_for(args.workload, args.mode, plan["variant"]),
-                "kernel": f"sweep {plan['variant']} (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
-                "flops_per_row": fl, "rows_per_launch": rows,
-                "work": "algorithmic flops per row = 3W + 20 edges (the per-row window contraction); "
-                        "sweeps that share work between inputs or states execute fewer, so frac can "
-                        "exceed 1; 'executed' counts the FP32 flops the profiler measured per row"}
-        t = _profiled(args.workload, args.mode, plan["variant"])
-        if t is not None and "exec_flops_per_row" in t:
-            ex = t["exec_flops_per_row"] * rows / (sweep_ms * 1e-3) / 1e12
-            roof["executed"] = {"flops_per_row": t["exec_flops_per_row"], "achieved": round(ex, 3),
-                                "frac": round(ex / PEAK_FP32_TFLOPS, 4)}
-    else:
-        by = stored_bytes_per_row(plan, False)
-        achieved = by * rows / (sweep_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": traffic_for(args.workload, args.mode, plan["variant"]),
-                "kernel": "k_sweep_stored (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
-                "bytes_per_row": by, "rows_per_launch": rows}
-
-    out = {
-        "metric": "Bellman (state,input) row-updates/sec FP32 vs FP64 at <=1e-5 err; p50/p99",
-        "value": value,
-        "unit": "row-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{p32.name} {p32.spec} {args.mode} (n_x={p32.n_x}, n_u={p32.n_u}, "
-                               f"T_d={T}, W={plan['W']})",
-                   "states": p32.n_x, "inputs": p32.n_u, "horizon": T, "rows": rows,
-                   "window": plan["window"][:p32.n], "W": plan["W"], "mode": args.mode,
-                   "variant": plan["variant"]},
-        "p50_ms": percentile(r32["lat"], 0.5),
-        "p99_ms": percentile(r32["lat"], 0.99),
-        "tail_bound_E": r32["info"]["tail_bound_E"],
-        "roofline": roof,
-    }
-    if not args.no_fp64:
-        p64 = p32.with_(precision="fp64")
-        s64 = A.Solver(p64, variant=args.variant)
-        r64 = run_solves(s64, max(3, args.steps // 2), 1)
-        v64 = rows * T * max(3, args.steps // 2) / r64["wall"]
-        err = float((r32["V"] - r64["V"]).abs().max().item())
-        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["wall"] / max(3, args.steps // 2),
-                       "p50_ms": percentile(r64["lat"], 0.5), "p99_ms": percentile(r64["lat"], 0.99)}
-        out["speedup_fp32_vs_fp64"] = value / v64
-        out["max_abs_err_fp32_vs_fp64"] = err
+    head, p32 = bench_solve(args.workload, args.mode, args.variant, args.steps, args.warmup,
+                            fp64=not args.no_fp64, check=not args.no_oracle_check)
+    print(f"[bench] {args.workload}: {head['value']:.4g} row-updates/s", file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": head.pop("value"), "unit": "row-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": head.pop("config")}
+    out.update(head)
+    if "max_abs_err_fp32_vs_fp64" in out:
         out["err_tol"] = 1e-5
-        out["err_ok"] = bool(err <= 1e-5)
-        del s64
+        out["err_ok"] = bool(out["max_abs_err_fp32_vs_fp64"] <= 1e-5 and
+                             out.get("err_vs_oracle", {}).get("ok", True))
+    also = {}
+    for w in [x for x in args.also.split(",") if x and x != args.workload]:
+        r, pw = bench_solve(w, "otf", "auto", args.steps, args.warmup, fp64=not args.no_fp64,
+                            check=not args.no_oracle_check)
+        r["config"]["features"] = {"disturbance_points": pw.n_w, "noise": pw.noise, "window": pw.window,
+                                   "dynamics": pw.dyn}
+        print(f"[bench] {w}: {r['value']:.4g} row-updates/s", file=sys.stderr, flush=True)
+        also[w] = r
+    if also:
+        out["also"] = also
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p32.with_(precision="fp64"))
     print(json.dumps(out), flush=True)

@@ -87,7 +87,13 @@ typedef enum { AMY_FP64 = 0, AMY_FP32 = 1 } amy_precision;
  *  AMY_DYN_VEHICLE7  n = 7, m = 2: the single-track model of the paper's
  *                    Sec. 8.4.1 with its printed right-hand sides, saturations
  *                    = clamps to the input box; params = {tau, l_wb, m, mu_bar,
- *                    l_f, l_r, h_cg, I_z, C_Sf, C_Sr, g}. */
+ *                    l_f, l_r, h_cg, I_z, C_Sf, C_Sr, g}.
+ *  AMY_DYN_ROBOT     n = 2, m = 2, p <= 1: the robot of Sec. 7, params = {tau},
+ *                    mu = (x1 + (tau u1) cos u2 + w, x2 + (tau u1) sin u2 + w)
+ *                    (the printed second row's factor u2 read as the speed u1;
+ *                    no w term without a disturbance).
+ * With a disturbance (p > 0) only AFFINE and ROBOT take it: AFFINE appends
+ * D[n*p] (row-major) to its params and adds (sum_l D_il w_l) last. */
 /* Bellman-sweep kernel variant.  AUTO lets the library (and its autotuner
  * cache) choose; the others force one, for tests and tuning:
  *   LANES    one lane per state, window lengths at run time (any shape whose
@@ -102,22 +108,53 @@ typedef enum { AMY_FP64 = 0, AMY_FP32 = 1 } amy_precision;
  *            last input digit (the unicycle's heading with the turn rate):
  *            the outer contraction is shared by all values of that digit.
  *            Same values up to summation order (not bitwise equal to LANES).
- * LANES, FIXED and the GROUP variants give bitwise equal results. */
+ *   INPUTS   one wavefront per state, its lanes splitting the state's inputs
+ *            (Alg. 4's parallel loop over X x U): for problems with few
+ *            states and many (input, disturbance) rows; normal noise only.
+ * LANES, FIXED, INPUTS and the GROUP variants give bitwise equal results. */
 typedef enum {
   AMY_VARIANT_AUTO = 0,
   AMY_VARIANT_LANES = 1,
   AMY_VARIANT_FIXED = 2,
   AMY_VARIANT_GROUP16 = 3,
   AMY_VARIANT_GROUP64 = 4,
-  AMY_VARIANT_FACTORED = 5
+  AMY_VARIANT_FACTORED = 5,
+  AMY_VARIANT_INPUTS = 6
 } amy_variant;
 
 typedef enum {
   AMY_DYN_AFFINE = 0,
   AMY_DYN_UNICYCLE = 1,
   AMY_DYN_ROOM = 2,
-  AMY_DYN_VEHICLE7 = 3
+  AMY_DYN_VEHICLE7 = 3,
+  AMY_DYN_ROBOT = 4,
+  AMY_DYN_USER = 5     /* right-hand side given as source text: amy_user_dynamics_create */
 } amy_dyn_kind;
+
+/* Noise distributions (Sec. 3 after Eq. 3.2 and Sec. 6.2: normal, uniform,
+ * exponential and beta), independent across dimensions:
+ *  NORMAL       zero mean, variance noise_var[i] (the default);
+ *  UNIFORM      uniform on [a[i], b[i]];
+ *  EXPONENTIAL  density rate e^{-rate t} for t >= 0, rate = a[i] > 0;
+ *  BETA         beta(alpha[i], beta[i]) stretched onto [a[i], b[i]],
+ *               alpha, beta >= 1 (a bounded density). */
+typedef enum {
+  AMY_NOISE_NORMAL = 0,
+  AMY_NOISE_UNIFORM = 1,
+  AMY_NOISE_EXPONENTIAL = 2,
+  AMY_NOISE_BETA = 3
+} amy_noise_kind;
+
+/* Which cells a row keeps around its mean mu (Sec. 5.2):
+ *  CENTRE     the paper's rule: cells whose centre lies in the cutting
+ *             interval [mu - x*, mu + x*] (normal noise only);
+ *  INTERSECT  cells that meet the cutting interval, so that no cell with
+ *             mass inside it is dropped.  The other distributions always
+ *             use INTERSECT with their support as the interval (Sec. 6.2:
+ *             the cut is tuned to the support of the density); the
+ *             exponential's support [0, inf) is cut where its density
+ *             falls to the cutoff gamma. */
+typedef enum { AMY_WINDOW_CENTRE = 0, AMY_WINDOW_INTERSECT = 1 } amy_window_rule;
 
 /* State grid: dimension i has count[i] cells [lo[i] + j h[i], lo[i] + (j+1) h[i]);
  * states are numbered row-major, the last dimension fastest. */
@@ -137,6 +174,32 @@ typedef struct {
   double lo[AMY_MAX_IN];
   double hi[AMY_MAX_IN];
 } amy_inputs;
+
+/* Disturbance set W-hat (Def. 3.1, its representative points): dimension l
+ * is the inclusive linspace lo[l] .. hi[l] with count[l] points (one point
+ * is lo); p = 0 means no disturbance.  The disturbance is an adversary
+ * (the Remark after Def. 3.2): a step takes V(x) = max_u min_w V_in(x,u,w)
+ * (Alg. 3 and Alg. 4).  m + p <= AMY_MAX_IN. */
+typedef struct {
+  int32_t p;
+  int32_t count[AMY_MAX_IN];
+  double lo[AMY_MAX_IN];
+  double hi[AMY_MAX_IN];
+} amy_disturbance;
+
+/* Noise model; all zero = additive normal noise with the paper's cut. */
+typedef struct {
+  int32_t kind;                  /* amy_noise_kind                           */
+  int32_t window;                /* amy_window_rule (NORMAL only)            */
+  int32_t multiplicative;        /* NORMAL only: Upsilon = varsigma x (Eq. 3.2):
+                                    dimension i's noise has standard deviation
+                                    sqrt(noise_var[i]) |x_i| at state x; the
+                                    cut is disabled (Sec. 6.2), rows span the
+                                    whole grid                               */
+  int32_t reserved;
+  double a[AMY_MAX_DIM], b[AMY_MAX_DIM];        /* support / rate            */
+  double alpha[AMY_MAX_DIM], beta[AMY_MAX_DIM]; /* BETA shapes               */
+} amy_noise;
 
 /* Closed box; set lo > hi in any dimension for the empty box. */
 typedef struct {
@@ -164,6 +227,8 @@ typedef struct {
   int32_t mode;                  /* amy_mode                                 */
   int32_t precision;             /* amy_precision                            */
   int32_t variant;               /* amy_variant (0 = AUTO)                   */
+  amy_disturbance dist;          /* p = 0: none                              */
+  amy_noise noise;               /* zero: additive normal, centre rule       */
 } amy_problem;
 
 typedef struct {
@@ -174,7 +239,7 @@ typedef struct {
                                     once per state for every input-digit
                                     combination its mean depends on          */
   int32_t lds_bytes;             /* dynamic LDS per 64-state workgroup       */
-  int64_t n_x, n_u, rows, W;     /* states, inputs, rows = n_x n_u, slots    */
+  int64_t n_x, n_u, rows, W;     /* states, inputs, rows = n_x n_u n_w, slots*/
   uint64_t workspace_bytes;      /* bytes amy_solve needs for this problem   */
   uint64_t stored_bytes;         /* of which transition rows (STORED mode)   */
   double max_row_tail;           /* max over rows of the cut-off mass (FP64) */
@@ -185,15 +250,45 @@ typedef struct {
    * of the working-precision sweep alone (the first step also computes the
    * FP64 tail, the last one writes FP64 V; 0 when T_d < 3). */
   double t_build_ms, t_sweeps_ms, t_main_sweeps_ms, t_readout_ms, t_total_ms;
+  int64_t n_w;                   /* disturbance points (1 without)           */
 } amy_info;
 
-/* Validate p and fill sizes, the mode AUTO resolves to for a workspace of
- * at most ws_budget bytes (0 = unlimited) and the workspace size.  No device
+/* Cells of the paper's quantisation convention (the robot example of
+ * Sec. 7, the case studies of Sec. 8 and the pair counts of Table 4): a box
+ * [lb, ub] with quantisation parameter q has the representative points
+ * lb + j q, j = 0 .. floor((ub - lb)/q + 1e-9), both ends included.  As
+ * cells: lo = lb - q/2, h = q, count = floor((ub - lb)/q + 1e-9) + 1 (the
+ * 1e-9 absorbs the binary rounding of ratios such as 0.6/0.1 = 5.999...).
+ * lb, ub, q: host arrays of n doubles (caller-owned, read only); out: host
+ * struct, filled on success (its other fields zeroed).  Pure host
+ * arithmetic, no device work.  AMY_E_INVALID when n is outside 1..8, an
+ * array or out is NULL, q <= 0, ub < lb, a value is not finite or a count
+ * exceeds 2^31 - 1. */
+amy_status amy_grid_from_quantization(int32_t n, const double* lb, const double* ub, const double* q,
+                                      amy_grid* out);
+
+/* The same convention for an input set (Sec. 7: input quantisation
+ * parameter): m dimensions (1..4), points lb + j q as the inclusive linspace
+ * lo = lb, hi = lb + (count - 1) q.  Errors as above. */
+amy_status amy_inputs_from_quantization(int32_t m, const double* lb, const double* ub, const double* q,
+                                        amy_inputs* out);
+
+/* Problem statement of Alg. 2 and Alg. 4 (state, input and noise sets,
+ * cutoff gamma of Sec. 5.2, horizon T_d, specification and its sets):
+ * validate p and fill sizes, the mode AUTO resolves to for a workspace of
+ * at most ws_budget bytes (0 = unlimited) and the workspace size.
+ * p, out: host structs owned by the caller (out may be NULL).  No device
  * work.  AMY_E_INVALID for a malformed problem; AMY_E_NOMEM when even the
- * OTF mode needs more than ws_budget. */
+ * OTF mode needs more than ws_budget; AMY_E_UNSUPPORTED for a valid problem
+ * this build cannot solve (window tables larger than LDS, more than 2^31
+ * states, more than 32767 inputs). */
 amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_info* out);
 
-/* Solve p on the HIP stream `stream` (hipStream_t; NULL = default stream).
+/* Alg. 4 (synthesis) over the abstraction of Alg. 2 -- rows built once and
+ * streamed (STORED) or rebuilt inside every step (OTF, Sec. 6.1) -- for the
+ * specification of Alg. 3: backward value iteration k = T_d .. 1, the max
+ * over inputs and its argmax of the collect step.
+ * Solve p on the HIP stream `stream` (hipStream_t; NULL = default stream).
  * workspace: device memory of ws_bytes >= amy_query's workspace_bytes
  * (computed with the same budget).  V_out: device double[n_x], V at k = 1.
  * policy_out: device int16[T_d * n_x] or NULL; entry (k-1)*n_x + x is the
@@ -203,6 +298,33 @@ amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_info* out);
  * and the phase times (HIP events on `stream`). */
 amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
                      double* V_out, int16_t* policy_out, amy_info* info);
+
+/* ------------------------------------------------- dynamics as source text
+ * Sec. 3: the user gives the right-hand side of the difference equation as
+ * text.  rhs is the body of a device function
+ *     void rhs(const double* x, const double* u, const double* w,
+ *              const double* params, double* mu)
+ * that reads the state's cell centre x[0..n), the input u[0..m), the
+ * disturbance w[0..p) and the problem's dyn.params[0..n_params), and writes
+ * the mean mu[0..n) (C++ in FP64, the C math functions available; it is
+ * compiled without fused multiply-adds).  The text is compiled for gfx950
+ * with hipRTC and loaded on the current device; it runs with the library's
+ * privileges, so it must come from a trusted source.  create: AMY_E_INVALID
+ * when the text does not compile (the compiler's message in
+ * amy_last_error), AMY_E_DEVICE when the module cannot be loaded.  The
+ * handle is owned by the caller until destroy. */
+typedef struct amy_user_dynamics amy_user_dynamics;
+amy_status amy_user_dynamics_create(const char* rhs, int32_t n, int32_t m, int32_t p, amy_user_dynamics** out);
+amy_status amy_user_dynamics_destroy(amy_user_dynamics* f);
+
+/* amy_solve for a problem whose dyn.kind is AMY_DYN_USER (amy_solve refuses
+ * those), with the rows built by the compiled right-hand side f: on the
+ * fly, with the run-time-window sweeps (one lane per state, or 16 or 64
+ * lanes per state for large windows; amy_query sizes the workspace).  p's n, m and
+ * dist.p must be those f was compiled for, on the current device.  Other
+ * arguments and errors as amy_solve. */
+amy_status amy_solve_user(const amy_user_dynamics* f, const amy_problem* p, void* stream, void* workspace,
+                          uint64_t ws_bytes, double* V_out, int16_t* policy_out, amy_info* info);
 
 /* ---------------------------------------------------------------- batch
  * Many independent systems (uneven grids, inputs and horizons) in ONE
@@ -214,14 +336,21 @@ amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64
  * the compiled families are affine n = 1..4, unicycle, room n = 2..5 and
  * the 7-D vehicle.  Horizons up to 1024, up to 4096 systems. */
 
-/* Workspace bytes of a batch (no device work). */
+/* Workspace bytes of a batch of count problems (host array, caller-owned;
+ * each validated as amy_query does).  No device work.  AMY_E_INVALID for a
+ * malformed problem or count outside 1..4096, AMY_E_UNSUPPORTED for a
+ * family, mode or horizon the batched kernel does not take. */
 amy_status amy_batch_query(const amy_problem* probs, int32_t count, uint64_t* ws_bytes);
 
-/* Solve count systems.  V_out[i]: device double[n_x(i)]; policy_out: NULL
+/* Alg. 4 for count independent systems in one launch (the batched form of
+ * the synthesis loop; every system's rows as amy_solve computes them).
+ * workspace: device memory of ws_bytes >= amy_batch_query's size.
+ * Solve count systems.  V_out[i]: device double[n_x(i)]; policy_out: NULL
  * or count device int16 buffers (each T_d(i) * n_x(i), entries may be NULL).
  * infos: NULL (asynchronous) or count amy_info, filled after waiting for the
  * stream (including each system's FP64 tail bound; t_total_ms is the time
- * of the whole launch).  AMY_E_DEVICE if a grid-barrier wait gave up. */
+ * of the whole launch).  AMY_E_DEVICE if a grid-barrier wait gave up; in
+ * the asynchronous mode (infos == NULL) every V_out then holds NaN. */
 amy_status amy_batch_solve(const amy_problem* probs, int32_t count, void* stream, void* workspace,
                            uint64_t ws_bytes, double* const* V_out, int16_t* const* policy_out,
                            amy_info* infos);
@@ -238,6 +367,13 @@ typedef struct {
   double best_ms, worst_ms;
 } amy_tune_result;
 
+/* The paper leaves the mapping of Alg. 4's parallel loops onto the device
+ * to its runtime; these calls pick it by measurement.
+ * amy_tune_solve: times every feasible sweep variant of p (each a full solve
+ * on `stream` in the caller's workspace, sized by amy_query) and caches the
+ * fastest for p's shape class.  amy_tune_batch: the same for a batch's
+ * launch parameters; a candidate whose grid barrier gave up is discarded.
+ * Synchronous; AMY_E_DEVICE on a HIP failure. */
 amy_status amy_tune_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
                           double* V_out, amy_tune_result* out);
 amy_status amy_tune_batch(const amy_problem* probs, int32_t count, void* stream, void* workspace,
@@ -279,8 +415,15 @@ typedef struct {
   double p50_ms, p99_ms, mean_ms;/* submit-to-result latency, completed      */
 } amy_server_stats;
 
+/* Serving form of Alg. 4 with the memory trade-off of Sec. 6.1 (stored rows
+ * when they fit, on-the-fly rows otherwise) decided per request.
+ * create: allocates the arena on cfg->device and starts the worker;
+ * AMY_E_INVALID for a bad cfg, AMY_E_DEVICE / AMY_E_NOMEM when the arena
+ * cannot be allocated.  *out is owned by the caller until amy_server_destroy. */
 amy_status amy_server_create(const amy_server_cfg* cfg, amy_server** out);
-/* Copies the problem; want_policy != 0 keeps the T_d x n_x policy. */
+/* Queue a request (validated as amy_query does; AMY_E_NOMEM when it can never
+ * fit the arena, AMY_E_UNSUPPORTED for a family the batched step lacks).
+ * Copies the problem; want_policy != 0 keeps the T_d x n_x policy. */
 amy_status amy_server_submit(amy_server* s, const amy_problem* p, int32_t want_policy, uint64_t* ticket);
 /* Result of a finished request into host buffers (V_host: n_x doubles;
  * policy_host: T_d * n_x int16 or NULL); the ticket is then released.
@@ -297,10 +440,11 @@ amy_status amy_server_reset_stats(amy_server* s);
 /* Finishes the admitted requests, drops the queued ones, frees everything. */
 amy_status amy_server_destroy(amy_server* s);
 
-/* Message of the last failed call on this thread ("" if none). */
+/* Message of the last failed call on this thread ("" if none); the string
+ * is owned by the library and valid until the thread's next failing call. */
 const char* amy_last_error(void);
 
-/* Library version string. */
+/* Library version string (static storage). */
 const char* amy_version(void);
 
 #ifdef __cplusplus

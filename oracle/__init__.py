@@ -20,7 +20,7 @@ BUILT_LIB = os.path.join(HERE, "libamy_oracle.so")
 LIB_PATH = os.environ.get("AMY_ORACLE_LIB") or BUILT_LIB
 
 MAX_DIM, MAX_IN, MAX_PARAMS = 8, 4, 128
-_DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3, "robot": 4}
+_DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3, "robot": 4, "user": 5}
 _SPEC = {"safety": 0, "reach": 1, "reach_avoid": 2}
 _NOISE = {"normal": 0, "uniform": 1, "exponential": 2, "beta": 3}
 _WINDOW = {"centre": 0, "intersect": 1}
@@ -43,6 +43,7 @@ class OrcProblem(C.Structure):
         ("noise", C.c_int32), ("window", C.c_int32), ("mult", C.c_int32),
         ("na", C.c_double * MAX_DIM), ("nb", C.c_double * MAX_DIM),
         ("nalpha", C.c_double * MAX_DIM), ("nbeta", C.c_double * MAX_DIM),
+        ("user_f", C.c_void_p),
     ]
 
 
@@ -127,7 +128,38 @@ def to_struct(p) -> OrcProblem:
     for src, dst in (("noise_a", s.na), ("noise_b", s.nb), ("noise_alpha", s.nalpha), ("noise_beta", s.nbeta)):
         for i, v in enumerate(tuple(getattr(p, src, ()) or ())):
             dst[i] = float(v)
+    if p.dyn == "user":
+        s.user_f = user_rhs(p.rhs)
     return s
+
+
+_user_libs = {}
+
+
+def user_rhs(text: str) -> int:
+    """Address of the right-hand side `text` compiled by gcc as
+    void f(const double* x, const double* u, const double* w,
+           const double* params, double* mu) { text }
+    (FP64, no contraction), built once per text into a cache directory."""
+    import hashlib
+    import tempfile
+    key = hashlib.sha256(text.encode()).hexdigest()[:16]
+    if key not in _user_libs:
+        d = os.path.join(tempfile.gettempdir(), f"amy_oracle_user_{os.getuid()}")
+        os.makedirs(d, exist_ok=True)
+        so = os.path.join(d, f"rhs_{key}.so")
+        if not os.path.exists(so):
+            src = os.path.join(d, f"rhs_{key}.c")
+            with open(src, "w") as fh:
+                fh.write("#include <math.h>\nvoid amy_user_rhs(const double* x, const double* u, const double* w,"
+                         " const double* params, double* mu) {\n" + text + "\n}\n")
+            tmp = so + f".{os.getpid()}.tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+                                   "-fno-fast-math", "-w", "-o", tmp, src, "-lm"])
+            os.replace(tmp, so)
+        lib_ = C.CDLL(so)
+        _user_libs[key] = (lib_, C.cast(lib_.amy_user_rhs, C.c_void_p).value)
+    return _user_libs[key][1]
 
 
 def _ptr(a, ct):

@@ -100,6 +100,7 @@ static int valid(const orc_problem* p) {
     case ORC_ROOM: if (p->n_params != 5 || !(p->m == 1 || p->m == p->n) || p->p != 0) return 0; break;
     case ORC_VEHICLE7: if (p->n != 7 || p->m != 2 || p->n_params != 11 || p->p != 0) return 0; break;
     case ORC_ROBOT: if (p->n != 2 || p->m != 2 || p->n_params != 1 || p->p > 1) return 0; break;
+    case ORC_USER: if (!p->user_f || p->n_params < 0 || p->n_params > ORC_MAX_PARAMS) return 0; break;
     default: return 0;
   }
   return 1;
@@ -204,6 +205,9 @@ int orc_mean(const orc_problem* p, const double* x, const double* u, const doubl
       }
       return 0;
     }
+    case ORC_USER:
+      p->user_f(x, u, w, q, mu);
+      return 0;
     case ORC_ROBOT: {
       /* the robot of Sec. 7: x1 + tau v1 cos(v2) + w, x2 + tau v1 sin(v2) + w
        * (the printed second row multiplies by v2; read as v1, the speed, as

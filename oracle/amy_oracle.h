@@ -42,7 +42,11 @@ extern "C" {
 #define ORC_MAX_IN 4
 #define ORC_MAX_PARAMS 128
 
-enum { ORC_AFFINE = 0, ORC_UNICYCLE = 1, ORC_ROOM = 2, ORC_VEHICLE7 = 3, ORC_ROBOT = 4 };
+enum { ORC_AFFINE = 0, ORC_UNICYCLE = 1, ORC_ROOM = 2, ORC_VEHICLE7 = 3, ORC_ROBOT = 4, ORC_USER = 5 };
+
+/* A right-hand side given by the user (Sec. 3: f as text, compiled by the
+ * host compiler for the oracle): mu = f(x, u, w) with the problem's params. */
+typedef void (*orc_user_fn)(const double* x, const double* u, const double* w, const double* params, double* mu);
 enum { ORC_SAFETY = 0, ORC_REACH = 1, ORC_REACH_AVOID = 2 };
 
 typedef struct {
@@ -76,6 +80,7 @@ typedef struct {
    * at state x, no cut */
   int32_t noise, window, mult;
   double na[ORC_MAX_DIM], nb[ORC_MAX_DIM], nalpha[ORC_MAX_DIM], nbeta[ORC_MAX_DIM];
+  orc_user_fn user_f;              /* ORC_USER only                          */
 } orc_problem;
 
 /* Full solve.  V_out[n_x] (host) receives V at k = 1.  policy_out (may be

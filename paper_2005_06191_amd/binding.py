@@ -19,12 +19,14 @@ MAX_DIM, MAX_IN, MAX_PARAMS = 8, 4, 128
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_NOTREADY = range(7)
 STATUS = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "BUSY", 6: "NOTREADY"}
-DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3}
+DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3, "robot": 4, "user": 5}
+NOISE = {"normal": 0, "uniform": 1, "exponential": 2, "beta": 3}
+WINDOW = {"centre": 0, "intersect": 1}
 SPEC = {"safety": 0, "reach": 1, "reach_avoid": 2}
 MODE = {"auto": 0, "stored": 1, "otf": 2}
 MODE_NAME = {v: k for k, v in MODE.items()}
 PREC = {"fp64": 0, "fp32": 1}
-VARIANT = {"auto": 0, "lanes": 1, "fixed": 2, "group16": 3, "group64": 4, "factored": 5}
+VARIANT = {"auto": 0, "lanes": 1, "fixed": 2, "group16": 3, "group64": 4, "factored": 5, "inputs": 6}
 VARIANT_NAME = {v: k for k, v in VARIANT.items()}
 
 
@@ -46,12 +48,24 @@ class Dynamics(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_params", C.c_int32), ("params", C.c_double * MAX_PARAMS)]
 
 
+class Disturbance(C.Structure):
+    _fields_ = [("p", C.c_int32), ("count", C.c_int32 * MAX_IN),
+                ("lo", C.c_double * MAX_IN), ("hi", C.c_double * MAX_IN)]
+
+
+class Noise(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("window", C.c_int32), ("multiplicative", C.c_int32),
+                ("reserved", C.c_int32), ("a", C.c_double * MAX_DIM), ("b", C.c_double * MAX_DIM),
+                ("alpha", C.c_double * MAX_DIM), ("beta", C.c_double * MAX_DIM)]
+
+
 class ProblemC(C.Structure):
     _fields_ = [("grid", Grid), ("inputs", Inputs), ("dyn", Dynamics),
                 ("noise_var", C.c_double * MAX_DIM), ("cutoff", C.c_double),
                 ("horizon", C.c_int32), ("spec", C.c_int32),
                 ("target", Box), ("avoid", Box), ("safe", Box),
-                ("mode", C.c_int32), ("precision", C.c_int32), ("variant", C.c_int32)]
+                ("mode", C.c_int32), ("precision", C.c_int32), ("variant", C.c_int32),
+                ("dist", Disturbance), ("noise", Noise)]
 
 
 class Info(C.Structure):
@@ -62,7 +76,7 @@ class Info(C.Structure):
                 ("max_row_tail", C.c_double), ("tail_bound_E", C.c_double),
                 ("t_build_ms", C.c_double), ("t_sweeps_ms", C.c_double),
                 ("t_main_sweeps_ms", C.c_double), ("t_readout_ms", C.c_double),
-                ("t_total_ms", C.c_double)]
+                ("t_total_ms", C.c_double), ("n_w", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -149,6 +163,18 @@ def lib():
         for fn in ("amy_server_create", "amy_server_submit", "amy_server_wait", "amy_server_poll",
                    "amy_server_get_stats", "amy_server_reset_stats", "amy_server_destroy"):
             getattr(L, fn).restype = C.c_int
+        dp = C.POINTER(C.c_double)
+        L.amy_grid_from_quantization.argtypes = [C.c_int32, dp, dp, dp, C.POINTER(Grid)]
+        L.amy_grid_from_quantization.restype = C.c_int
+        L.amy_inputs_from_quantization.argtypes = [C.c_int32, dp, dp, dp, C.POINTER(Inputs)]
+        L.amy_inputs_from_quantization.restype = C.c_int
+        L.amy_user_dynamics_create.argtypes = [C.c_char_p, C.c_int32, C.c_int32, C.c_int32,
+                                               C.POINTER(C.c_void_p)]
+        L.amy_user_dynamics_create.restype = C.c_int
+        L.amy_user_dynamics_destroy.argtypes = [C.c_void_p]
+        L.amy_user_dynamics_destroy.restype = C.c_int
+        L.amy_solve_user.argtypes = [C.c_void_p, pp, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p, ip]
+        L.amy_solve_user.restype = C.c_int
         L.amy_last_error.restype = C.c_char_p
         L.amy_version.restype = C.c_char_p
         _lib = L
@@ -196,6 +222,18 @@ def to_struct(p, mode=None, precision=None, variant=None) -> ProblemC:
     s.mode = MODE[mode or p.mode]
     s.precision = PREC[precision or p.precision]
     s.variant = VARIANT[variant or getattr(p, "variant", "auto")]
+    wc = tuple(getattr(p, "w_count", ()) or ())
+    s.dist.p = len(wc)
+    for l in range(len(wc)):
+        s.dist.count[l], s.dist.lo[l], s.dist.hi[l] = int(wc[l]), float(p.w_lo[l]), float(p.w_hi[l])
+    s.noise.kind = NOISE[getattr(p, "noise", "normal")]
+    s.noise.window = WINDOW[getattr(p, "window", "centre")]
+    s.noise.multiplicative = int(bool(getattr(p, "multiplicative", False)))
+    for name in ("a", "b", "alpha", "beta"):
+        vals = tuple(getattr(p, "noise_" + name, ()) or ())
+        arr = getattr(s.noise, name)
+        for i, v in enumerate(vals):
+            arr[i] = float(v)
     return s
 
 
@@ -214,12 +252,14 @@ class Result:
 
 
 class Solver:
-    """Holds a device workspace for repeated solves of problems of one size."""
+    """Holds a device workspace for repeated solves of problems of one size
+    (user: the UserDynamics of a problem whose dynamics are source text)."""
 
-    def __init__(self, p, budget: int = 0, device=None, **kw):
+    def __init__(self, p, budget: int = 0, device=None, user=None, **kw):
         import torch
         self.torch = torch
         self.p = p
+        self.user = user
         self.s = to_struct(p, **kw)
         self.device = torch.device(device or "cuda")
         info = Info()
@@ -237,10 +277,13 @@ class Solver:
         pol = torch.empty((T, n_x), dtype=torch.int16, device=self.device) if (policy and T > 0) else None
         st = stream if stream is not None else torch.cuda.current_stream(self.device)
         inf = Info() if info else None
-        rc = lib().amy_solve(C.byref(self.s), C.c_void_p(st.cuda_stream), C.c_void_p(self.ws_ptr),
-                             self.ws_bytes, C.c_void_p(V.data_ptr()),
-                             C.c_void_p(pol.data_ptr()) if pol is not None else None,
-                             C.byref(inf) if inf is not None else None)
+        args = (C.byref(self.s), C.c_void_p(st.cuda_stream), C.c_void_p(self.ws_ptr), self.ws_bytes,
+                C.c_void_p(V.data_ptr()), C.c_void_p(pol.data_ptr()) if pol is not None else None,
+                C.byref(inf) if inf is not None else None)
+        if self.user is not None:
+            rc = lib().amy_solve_user(self.user._h, *args)
+        else:
+            rc = lib().amy_solve(*args)
         check(rc)
         return Result(V, pol, inf.as_dict() if inf is not None else None)
 
@@ -248,6 +291,61 @@ class Solver:
 def solve(p, policy: bool = True, info: bool = True, budget: int = 0, **kw) -> Result:
     """One solve; keyword overrides: mode=, precision=, variant=."""
     return Solver(p, budget=budget, **kw).solve(policy=policy, info=info)
+
+
+def _quant_args(lb, ub, q):
+    n = len(lb)
+    arr = C.c_double * n
+    return n, arr(*map(float, lb)), arr(*map(float, ub)), arr(*map(float, q))
+
+
+def grid_from_quantization(lb, ub, q):
+    """amy_grid_from_quantization: (lo, h, count) tuples of the paper's
+    quantisation convention."""
+    n, a, b, c = _quant_args(lb, ub, q)
+    g = Grid()
+    check(lib().amy_grid_from_quantization(n, a, b, c, C.byref(g)))
+    return tuple(g.lo[:n]), tuple(g.h[:n]), tuple(int(x) for x in g.count[:n])
+
+
+def inputs_from_quantization(lb, ub, q):
+    """amy_inputs_from_quantization: (lo, hi, count) tuples."""
+    m, a, b, c = _quant_args(lb, ub, q)
+    u = Inputs()
+    check(lib().amy_inputs_from_quantization(m, a, b, c, C.byref(u)))
+    return tuple(u.lo[:m]), tuple(u.hi[:m]), tuple(int(x) for x in u.count[:m])
+
+
+class UserDynamics:
+    """amy_user_dynamics_create: a right-hand side given as source text (the
+    body of rhs(x, u, w, params, mu)), compiled on the current device."""
+
+    def __init__(self, rhs: str, n: int, m: int, p: int = 0):
+        self._h = C.c_void_p()
+        check(lib().amy_user_dynamics_create(rhs.encode(), int(n), int(m), int(p), C.byref(self._h)))
+
+    def solver(self, prob, budget: int = 0, **kw) -> "Solver":
+        return Solver(prob, budget=budget, user=self, **kw)
+
+    def solve(self, prob, policy: bool = True, info: bool = True, budget: int = 0, **kw) -> Result:
+        return self.solver(prob, budget=budget, **kw).solve(policy=policy, info=info)
+
+    def close(self):
+        if self._h:
+            check(lib().amy_user_dynamics_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -44,9 +44,9 @@ __device__ __forceinline__ void call_variant(const DevProblem& P, uint32_t s, co
                                              const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
                                              unsigned char* smem) {
   if constexpr (G == 1)
-    sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
+    sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL, false>(P, s, Vin, Vout, label, pol, tailmax, smem);
   else
-    sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, s, Vin, Vout, label, pol, tailmax, smem);
+    sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G, false>(P, s, Vin, Vout, label, pol, tailmax, smem);
 }
 
 template <int KIND, int N, int G, bool F64>
@@ -149,7 +149,7 @@ __device__ __forceinline__ void tail_tile(const BatchSys& B, uint32_t tile) {
   const uint32_t s = tile * BATCH_BLOCK + (threadIdx.x & 63);
   double tmax = 0.0;
 #define X(K, N_) \
-  case K * 16 + N_: tmax = tail_state<K, N_>(B.P, s, B.label); break;
+  case K * 16 + N_: tmax = tail_state<K, N_, false>(B.P, s, B.label); break;
   if constexpr (FS == 0) {
     switch (B.P.kind * 16 + B.P.n) { AMY_BATCH_FAMILIES_SMALL(X) }
   } else {
@@ -300,6 +300,21 @@ __global__ void __launch_bounds__(BATCH_BLOCK) k_batch_tail(const BatchSys* __re
   }
 }
 
+// After a persistent launch: if a grid-barrier wait gave up, every
+// system's FP64 output becomes NaN, so a caller that does not read the
+// control block (the asynchronous mode) still cannot take invalid values
+// for results.  Block b handles systems b, b + gridDim.x, ...
+__global__ void __launch_bounds__(256) k_batch_poison(const BatchSys* __restrict__ sys, int nsys,
+                                                      const BatchCtl* __restrict__ ctl) {
+  if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) return;
+  const double nan = __builtin_nan("");
+  for (int j = blockIdx.x; j < nsys; j += gridDim.x) {
+    double* v = sys[j].Vout;
+    const int64_t n = sys[j].P.n_x;
+    for (int64_t s = threadIdx.x; s < n; s += blockDim.x) v[s] = nan;
+  }
+}
+
 __global__ void k_fill_u32(unsigned* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = 0u;
@@ -350,6 +365,12 @@ hipError_t amy_launch_batch_tail(int fs, const BatchSys* sys, int nsys, const in
                                  hipStream_t st) {
   if (fs == 0) hipLaunchKernelGGL((k_batch_tail<0>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tp64);
   else hipLaunchKernelGGL((k_batch_tail<1>), dim3(grid), dim3(BATCH_BLOCK), 0, st, sys, nsys, tp64);
+  return hipGetLastError();
+}
+
+hipError_t amy_launch_batch_poison(const BatchSys* sys, int nsys, const BatchCtl* ctl, hipStream_t st) {
+  const unsigned g = (unsigned)(nsys < 1024 ? nsys : 1024);
+  hipLaunchKernelGGL(k_batch_poison, dim3(g > 0 ? g : 1), dim3(256), 0, st, sys, nsys, ctl);
   return hipGetLastError();
 }
 

@@ -23,3 +23,5 @@ hipError_t amy_launch_batch_init(bool f64, const BatchSys* sys, int nsys, const 
 hipError_t amy_launch_batch_tail(int fs, const BatchSys* sys, int nsys, const int32_t* tp64, unsigned grid,
                                  hipStream_t st);
 hipError_t amy_launch_fill_u32(unsigned* p, size_t n, hipStream_t st);
+// NaN into every system's V_out when the launch's control block has err set
+hipError_t amy_launch_batch_poison(const BatchSys* sys, int nsys, const BatchCtl* ctl, hipStream_t st);

@@ -14,6 +14,22 @@
 
 static inline uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+// Workgroups with `lds` bytes of LDS that one CU holds at once: gfx950
+// allocates a workgroup's LDS in granules of 1280 bytes (320 dwords) out of
+// the CU's 160 KiB, as a residency probe on MI355X confirms for every size
+// from 1 KiB to 40 KiB in 256-byte steps (the occupancy query, which
+// divides by the byte count, is above the resident count for 35 of them).
+int amy_lds_blocks_per_cu(int dev, size_t lds) {
+  const size_t granule = 1280;
+  int per_cu = 0;
+  if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 160 * 1024;
+  if (lds == 0) return 1 << 20;
+  const size_t alloc = (lds + granule - 1) / granule * granule;
+  return (int)((size_t)per_cu / alloc);
+}
+
 // A system in a batched launch runs one of the two run-time-window variants
 // compiled into the batched kernel, LANES or GROUP64: every variant computes
 // the same bits, and leaving the others out keeps the batched kernel's
@@ -29,6 +45,13 @@ amy_status amy_batch_normalise(const amy_problem* p, Plan* pl) {
   if (D.variant == AMY_VARIANT_FIXED || D.variant == AMY_VARIANT_FACTORED) {
     D.variant = AMY_VARIANT_LANES;
     D.rel_entries = 0;
+  }
+  if (D.variant == AMY_VARIANT_INPUTS) {
+    amy_problem q = *p;
+    q.mode = AMY_MODE_OTF;
+    q.variant = AMY_VARIANT_LANES;
+    const amy_status st = amy_resolve(&q, 0, pl);
+    if (st != AMY_OK) return st;
   }
   if (D.variant == AMY_VARIANT_GROUP16) {
     amy_problem q = *p;
@@ -56,11 +79,15 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
     if (q.mode == AMY_MODE_STORED)
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: the batched launch recomputes rows (OTF mode only)", i);
     q.mode = AMY_MODE_OTF;
-    if (q.variant == AMY_VARIANT_FIXED || q.variant == AMY_VARIANT_FACTORED) q.variant = AMY_VARIANT_LANES;
+    if (q.variant == AMY_VARIANT_FIXED || q.variant == AMY_VARIANT_FACTORED || q.variant == AMY_VARIANT_INPUTS)
+      q.variant = AMY_VARIANT_LANES;
     st = amy_resolve(&q, 0, &bp.plans[i]);
     if (st == AMY_OK) st = amy_batch_normalise(&q, &bp.plans[i]);
     if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
     const DevProblem& D = bp.plans[i].dev;
+    if (D.pd != 0 || D.noise != 0 || D.wrule != 0 || D.mult)
+      return amy_fail(AMY_E_UNSUPPORTED, "system %d: the batched launch takes additive normal noise with the "
+                      "centre rule and no disturbance", i);
     if (!amy_batch_supports(D.kind, D.n, AMY_MODE_OTF))
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: dynamics kind %d with n=%d is not compiled into the batched kernel",
                       i, D.kind, D.n);
@@ -71,9 +98,8 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
       return amy_fail(AMY_E_UNSUPPORTED, "system %d: horizon %d > %d", i, probs[i].horizon, AMY_BATCH_MAX_STEPS);
     bp.maxT = std::max(bp.maxT, (int)probs[i].horizon);
     bp.fs = std::max(bp.fs, amy_batch_family_set(D.kind, D.n));
-    // (the tail slots are reserved too, though the steps do not use them:
-    // the persistent grid is sized by this figure)
-    bp.lds = std::max(bp.lds, (size_t)(D.grp_g > 1 ? D.lds_bytes_group : D.lds_bytes_tail));
+    // the steps' LDS (the FP64 tail has a pass of its own)
+    bp.lds = std::max(bp.lds, (size_t)(D.grp_g > 1 ? D.lds_bytes_group : D.lds_bytes));
   }
   // longest horizon first: the systems still running at global step s are a prefix
   bp.order.resize(count);
@@ -160,11 +186,15 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
   hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, amy_batch_persistent_kernel(bp.f64, bp.fs), 64, bp.lds);
   if (e != hipSuccess || occ < 1) return amy_hip_fail(e, "batch occupancy query");
-  // at most 8 workgroups per CU: a cooperative grid of 14 per CU (all the
-  // occupancy query allowed for a batch of small tables) did not get every
-  // workgroup through its barriers; the grids sized with the full LDS
-  // reservation and this cap have
-  const int bpc = std::min(tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, occ) : occ, 8);
+  // Every workgroup of the cooperative grid must be resident at once (the
+  // grid barrier waits for all of them).  The occupancy query divides the
+  // CU's LDS by the block's byte count, but gfx950 allocates LDS in whole
+  // granules, so it can promise more blocks than fit; the grid is sized by
+  // the granule-rounded reservation as well.
+  const int bpc_lds = amy_lds_blocks_per_cu(dev, bp.lds);
+  if (bpc_lds < 1) return amy_fail(AMY_E_UNSUPPORTED, "batch needs %zu B of LDS per workgroup", bp.lds);
+  const int resident = std::min(occ, bpc_lds);
+  const int bpc = tune.blocks_per_cu > 0 ? std::min(tune.blocks_per_cu, resident) : resident;
   const unsigned grid = (unsigned)std::max(1, ncu * bpc);
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (ms_out) {
@@ -181,6 +211,8 @@ amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStrea
     e = amy_launch_batch_persistent(bp.f64, bp.fs, grid, bp.lds, dsys, count, (const int32_t*)(ws + bp.off_tp),
                                     (const int32_t*)(ws + bp.off_act), bp.maxT, (BatchCtl*)(ws + bp.off_ctl),
                                     std::max(1, tune.chunk), tune.xcd_order, hs);
+  if (e == hipSuccess && bp.maxT > 0)
+    e = amy_launch_batch_poison(dsys, count, (const BatchCtl*)(ws + bp.off_ctl), hs);
   if (e != hipSuccess) {
     if (ms_out) {
       hipEventDestroy(ev[0]);

@@ -17,9 +17,13 @@
 // Everything here is compiled with -ffp-contract=off; fused multiply-adds
 // appear only where written (fma_).
 #pragma once
+// (also compiled at run time by hipRTC, which supplies the HIP and math
+// declarations itself: __HIPCC_RTC__ marks that build)
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#endif
 
 #include "amy_plan.hpp"
 
@@ -27,6 +31,7 @@
 #define AMY_DYN_UNICYCLE_ 1
 #define AMY_DYN_ROOM_ 2
 #define AMY_DYN_VEHICLE7_ 3
+#define AMY_DYN_ROBOT_ 4
 
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -52,7 +57,9 @@ __device__ __forceinline__ void state_centre(const DevProblem& P, uint32_t s, do
   }
 }
 
-// Input points as an odometer over the m input dimensions (last fastest).
+// (input, disturbance) points as an odometer over the nd digits: the m
+// input dimensions, then the disturbance dimensions (last fastest).  u[k]
+// for k < m is the input, u[m + l] the disturbance's dimension l.
 struct InputWalk {
   int dig[AMY_MAXI];
   __device__ __forceinline__ void reset() {
@@ -62,13 +69,27 @@ struct InputWalk {
   __device__ __forceinline__ void values(const DevProblem& P, double* u) const {
 #pragma unroll
     for (int k = 0; k < AMY_MAXI; ++k)
-      u[k] = (k < P.m) ? ((P.ucount[k] == 1) ? P.ulo[k] : P.ulo[k] + (double)dig[k] * P.ustep[k]) : 0.0;
+      u[k] = (k < P.nd) ? ((P.ucount[k] == 1) ? P.ulo[k] : P.ulo[k] + (double)dig[k] * P.ustep[k]) : 0.0;
+  }
+  // the first row of input number u (input digits of u, disturbance digits 0)
+  __device__ __forceinline__ void set_input(const DevProblem& P, int u) {
+#pragma unroll
+    for (int k = AMY_MAXI - 1; k >= 0; --k) {
+      if (k >= P.nd) {
+        dig[k] = 0;
+      } else if (k >= P.m) {
+        dig[k] = 0;
+      } else {
+        dig[k] = u % P.ucount[k];
+        u /= P.ucount[k];
+      }
+    }
   }
   __device__ __forceinline__ void next(const DevProblem& P) {
     bool carry = true;
 #pragma unroll
     for (int k = AMY_MAXI - 1; k >= 0; --k) {
-      if (carry && k < P.m) {
+      if (carry && k < P.nd) {
         if (++dig[k] >= P.ucount[k]) dig[k] = 0;
         else carry = false;
       }
@@ -98,6 +119,7 @@ struct Dyn<AMY_DYN_AFFINE_, N> {
   __device__ __forceinline__ static void apply(const DevProblem& P, const State& st, const double*,
                                                const double* u, double* mu) {
     const double* B = P.params + N * N;
+    const double* D = P.params + N * N + N * P.m + N;  // disturbance columns (pd > 0)
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       double t = 0.0;
@@ -105,6 +127,31 @@ struct Dyn<AMY_DYN_AFFINE_, N> {
       for (int k = 0; k < AMY_MAXI; ++k)
         if (k < P.m) t = t + B[i * P.m + k] * u[k];
       mu[i] = st.s[i] + t;
+      if (P.pd > 0) {
+        double d = 0.0;
+#pragma unroll
+        for (int l = 0; l < AMY_MAXI; ++l)
+          if (l < P.pd) d = d + D[i * P.pd + l] * u[P.m + l];
+        mu[i] = mu[i] + d;
+      }
+    }
+  }
+};
+
+// The planar robot of Sec. 7: speed u0 along heading u1, pushed by the
+// disturbance w on both axes (w = 0 and no w term without a disturbance).
+template <>
+struct Dyn<AMY_DYN_ROBOT_, 2> {
+  struct State { int unused; };
+  __device__ __forceinline__ static void prep(const DevProblem&, const double*, State&) {}
+  __device__ __forceinline__ static void apply(const DevProblem& P, const State&, const double* x,
+                                               const double* u, double* mu) {
+    const double a = P.params[0] * u[0];
+    mu[0] = x[0] + a * cos(u[1]);
+    mu[1] = x[1] + a * sin(u[1]);
+    if (P.pd > 0) {
+      mu[0] = mu[0] + u[2];
+      mu[1] = mu[1] + u[2];
     }
   }
 };
@@ -198,30 +245,40 @@ struct Dyn<AMY_DYN_VEHICLE7_, 7> {
 
 // Kept cells of dimension i for mean mu: [jlo, b-1] (empty when b == jlo),
 // and the origin o of the fixed L_i-slot window, o <= jlo, o + L_i <= n_i.
-// z0 = (lo - mu) / sigma is the edge coordinate of grid edge 0.
-struct Win { int jlo, b, o; double z0; };
+// z0 = (lo - mu) / scale is the edge coordinate of grid edge 0 and hs the
+// edge spacing in those units.  isc: the inverse of the state's noise scale
+// factor (multiplicative noise: 1/|x_i|, infinite at x_i = 0; 1 otherwise).
+struct Win { int jlo, b, o; double z0, hs; };
 
-__device__ __forceinline__ Win window_1d(const DevProblem& P, int i, double mu) {
+__device__ __forceinline__ Win window_1d(const DevProblem& P, int i, double mu, double isc = 1.0) {
   const int n = P.count[i], L = P.L[i];
   Win w;
   if (P.nocut) {
     w.jlo = 0;
     w.b = n;
   } else {
-    // cell j is kept iff its centre lo + (j + 1/2) h lies in [mu - x*, mu + x*]
     const double m = mu * P.inv_h[i];
     double tl = m - P.win_a[i];
     double th = m - P.win_b[i];
     tl = fmin(fmax(tl, -1.0), (double)n);
     th = fmin(fmax(th, -2.0), (double)n);
-    const int jlo = max(0, (int)ceil(tl));
-    int jhi = min(n - 1, (int)floor(th));
+    int jlo, jhi;
+    if (P.wrule == 0) {
+      // cell j is kept iff its centre lo + (j + 1/2) h lies in [mu + zl, mu + zh]
+      jlo = max(0, (int)ceil(tl));
+      jhi = min(n - 1, (int)floor(th));
+    } else {
+      // cell j is kept iff (lo + j h, lo + (j + 1) h) meets (mu + zl, mu + zh)
+      jlo = max(0, (int)floor(tl));
+      jhi = min(n - 1, (int)ceil(th) - 1);
+    }
     jhi = min(jhi, jlo + L - 1);  // allocation bound, for rounding at exact ties
     w.jlo = jlo;
     w.b = max(jhi + 1, jlo);
   }
   w.o = min(w.jlo, n - L);
-  w.z0 = (P.lo[i] - mu) * P.inv_sigma[i];
+  w.z0 = (P.lo[i] - mu) * P.inv_sigma[i] * isc;
+  w.hs = P.hs[i] * isc;
   return w;
 }
 
@@ -244,8 +301,152 @@ __device__ __forceinline__ MT mass_of(double z0, MT e0, double z1, MT e1) {
   return MT(1) - MT(0.5) * (e0 + e1);
 }
 
-__device__ __forceinline__ double edge_z(const DevProblem& P, int i, const Win& w, int E) {
-  return w.z0 + (double)E * P.hs[i];
+__device__ __forceinline__ double edge_z(const DevProblem&, int, const Win& w, int E) {
+  return w.z0 + (double)E * w.hs;
+}
+
+// ---------------------------------------------------- other noise models
+//
+// FP64 lower and upper tail masses at a standardised edge z, for the
+// noise models other than additive normal (and for multiplicative normal
+// noise); the mass of a cell is the difference of the tail on the side of
+// the median away from which both its edges lie, or 1 minus both tails.
+
+struct Tails { double lo, up; };
+
+// Regularised incomplete beta I_x(a, b) by its continued fraction
+// (modified Lentz), for x below (a + 1) / (a + b + 2) where it converges fast.
+__device__ __noinline__ double ibeta_cf(double x, double a, double b) {
+  const double tiny = 1e-300;
+  double c = 1.0, d = 1.0 - (a + b) * x / (a + 1.0);
+  if (fabs(d) < tiny) d = tiny;
+  d = 1.0 / d;
+  double f = d;
+  for (int k = 1; k <= 400; ++k) {
+    const double kk = (double)k;
+    // even term k(b - k) x / ((a + 2k - 1)(a + 2k))
+    double num = kk * (b - kk) * x / ((a + 2.0 * kk - 1.0) * (a + 2.0 * kk));
+    d = 1.0 + num * d;
+    if (fabs(d) < tiny) d = tiny;
+    c = 1.0 + num / c;
+    if (fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    f *= d * c;
+    // odd term -(a + k)(a + b + k) x / ((a + 2k)(a + 2k + 1))
+    num = -(a + kk) * (a + b + kk) * x / ((a + 2.0 * kk) * (a + 2.0 * kk + 1.0));
+    d = 1.0 + num * d;
+    if (fabs(d) < tiny) d = tiny;
+    c = 1.0 + num / c;
+    if (fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    f *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  const double lbeta = lgamma(a) + lgamma(b) - lgamma(a + b);
+  return exp(a * log(x) + b * log1p(-x) - lbeta) * f / a;
+}
+
+__device__ __noinline__ Tails noise_tails(const DevProblem& P, int i, double z) {
+  Tails t;
+  switch (P.noise) {
+    case 1: {  // uniform on the unit support
+      const double x = fmin(fmax(z - P.zoff[i], 0.0), 1.0);
+      t.lo = x;
+      t.up = 1.0 - x;
+      break;
+    }
+    case 2: {  // exponential, unit rate in z
+      if (z <= 0.0) {
+        t.lo = 0.0;
+        t.up = 1.0;
+      } else {
+        t.lo = -expm1(-z);
+        t.up = exp(-z);
+      }
+      break;
+    }
+    case 3: {  // beta on the unit support
+      const double x = fmin(fmax(z - P.zoff[i], 0.0), 1.0);
+      const double a = P.balpha[i], b = P.bbeta[i];
+      if (x <= 0.0) {
+        t.lo = 0.0;
+        t.up = 1.0;
+      } else if (x >= 1.0) {
+        t.lo = 1.0;
+        t.up = 0.0;
+      } else if (x < (a + 1.0) / (a + b + 2.0)) {
+        t.lo = ibeta_cf(x, a, b);
+        t.up = 1.0 - t.lo;
+      } else {
+        t.up = ibeta_cf(1.0 - x, b, a);
+        t.lo = 1.0 - t.up;
+      }
+      break;
+    }
+    default: {  // normal: the small tail from erfc, exact on either side of 0
+      const double a = fabs(z) > 38.5 ? 0.0 : erfc(fabs(z) * 0.70710678118654752440) * 0.5;
+      t.lo = z <= 0.0 ? a : 1.0 - a;
+      t.up = z <= 0.0 ? 1.0 - a : a;
+      break;
+    }
+  }
+  return t;
+}
+
+// Median of the standardised noise (the side switch of the differencing).
+__device__ __forceinline__ double noise_median(const DevProblem& P, int i) {
+  switch (P.noise) {
+    case 1: return P.zoff[i] + 0.5;
+    case 2: return 0.69314718055994530942;
+    case 3: return P.zoff[i] + P.balpha[i] / (P.balpha[i] + P.bbeta[i]);
+  }
+  return 0.0;
+}
+
+__device__ __forceinline__ double tails_mass(double z0, const Tails& t0, double z1, const Tails& t1, double zm) {
+  if (z1 <= zm) return t1.lo - t0.lo;
+  if (z0 >= zm) return t0.up - t1.up;
+  return (1.0 - t0.lo) - t1.up;
+}
+
+// Mass of [edge E0, edge E1] of dimension i in the general model (FP64);
+// a zero noise scale (multiplicative noise at a zero coordinate, isc
+// infinite) puts the whole mass in the cell that holds the mean.
+__device__ __noinline__ double general_mass(const DevProblem& P, int i, const Win& w, int E0, int E1,
+                                            double mu, double isc) {
+  if (E1 <= E0) return 0.0;
+  if (isinf(isc)) {
+    const double a = P.lo[i] + (double)E0 * P.h[i], b = P.lo[i] + (double)E1 * P.h[i];
+    return (a <= mu && mu < b) ? 1.0 : 0.0;
+  }
+  const double zm = noise_median(P, i);
+  const double z0 = edge_z(P, i, w, E0), z1 = edge_z(P, i, w, E1);
+  return tails_mass(z0, noise_tails(P, i, z0), z1, noise_tails(P, i, z1), zm);
+}
+
+// The slot masses of dim_table in the general noise models: FP64 tails per
+// edge, each cell's mass rounded once (out of line: one copy per kernel
+// file, not one per inlined call site).
+template <class MT>
+__device__ __noinline__ void general_table(const DevProblem& P, int i, const Win& w, double mu, double isc, MT* t,
+                                           int ts) {
+  const int L = P.L[i];
+  if (isinf(isc)) {
+    for (int k = 0; k < L; ++k)
+      t[k * ts] = MT(general_mass(P, i, w, min(max(w.o + k, w.jlo), w.b), min(max(w.o + k + 1, w.jlo), w.b), mu, isc));
+    return;
+  }
+  const double zm = noise_median(P, i);
+  double zq = edge_z(P, i, w, min(max(w.o, w.jlo), w.b));
+  Tails tq = noise_tails(P, i, zq);
+  for (int k = 0; k < L; ++k) {
+    const double z = edge_z(P, i, w, min(max(w.o + k + 1, w.jlo), w.b));
+    const Tails tz = noise_tails(P, i, z);
+    t[k * ts] = MT(z > zq ? tails_mass(zq, tq, z, tz, zm) : 0.0);
+    zq = z;
+    tq = tz;
+  }
 }
 
 // 1-D masses of the L_i window slots of dimension i into t[k*ts] (slot k is
@@ -281,12 +482,36 @@ __device__ __forceinline__ void win_grid_mass(const DevProblem& P, int i, const 
   grid = mass_edges(P, i, w, 0, P.count[i]);
 }
 
+// The same for the run-time-window sweeps, which also take the other noise
+// models and multiplicative noise (isc: the state's inverse noise scale);
+// the compiled-shape sweeps, which run additive normal noise only, call
+// the plain forms above and carry no call to the general path.
+template <class MT>
+__device__ __forceinline__ Win dim_table_gen(const DevProblem& P, int i, double mu, MT* t, int ts, double isc) {
+  if (P.noise != 0 || P.mult) {
+    const Win w = window_1d(P, i, mu, isc);
+    general_table<MT>(P, i, w, mu, isc, t, ts);
+    return w;
+  }
+  return dim_table<MT>(P, i, mu, t, ts);
+}
+
+__device__ __forceinline__ void win_grid_mass_gen(const DevProblem& P, int i, const Win& w, double& win,
+                                                  double& grid, double mu, double isc) {
+  if (P.noise != 0 || P.mult) {
+    win = general_mass(P, i, w, w.jlo, w.b, mu, isc);
+    grid = general_mass(P, i, w, 0, P.count[i], mu, isc);
+    return;
+  }
+  win_grid_mass(P, i, w, win, grid);
+}
+
 // Input digits of table c of dimension i (digits the mean does not depend on are 0).
 __device__ __forceinline__ void combo_digits(const DevProblem& P, int i, int c, InputWalk& iw) {
 #pragma unroll
   for (int k = 0; k < AMY_MAXI; ++k) {
     const int mlt = P.dep_mult[i][k];
-    iw.dig[k] = (k < P.m && mlt > 0) ? (c / mlt) % P.ucount[k] : 0;
+    iw.dig[k] = (k < P.nd && mlt > 0) ? (c / mlt) % P.ucount[k] : 0;
   }
 }
 
@@ -356,11 +581,20 @@ struct LaneLds {
   }
 };
 
+// Inverse noise-scale factors of the state at x: 1 for additive noise,
+// 1/|x_i| for multiplicative noise (infinite at x_i = 0).
+template <int N>
+__device__ __forceinline__ void state_isc(const DevProblem& P, const double* x, double* isc) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) isc[i] = P.mult ? 1.0 / fabs(x[i]) : 1.0;
+}
+
 // Build every cached table of state x (all input-digit combinations of the
-// dimensions whose tables are cached).
+// dimensions whose tables are cached); isc: the state's inverse noise
+// scales (nullptr: additive noise, all 1).
 template <int KIND, int N, class MT, bool TAIL, int LB>
 __device__ __forceinline__ void build_cached(const DevProblem& P, const typename Dyn<KIND, N>::State& st,
-                                             const double* x, const LaneLds<MT>& S) {
+                                             const double* x, const double* isc, const LaneLds<MT>& S) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     const int C = P.ccount[i];
@@ -370,11 +604,14 @@ __device__ __forceinline__ void build_cached(const DevProblem& P, const typename
       double uv[AMY_MAXI], mu[N];
       iw.values(P, uv);
       Dyn<KIND, N>::apply(P, st, x, uv, mu);
-      const Win w = dim_table<MT>(P, i, mu[i], S.tab + (P.toff[i] + c * P.L[i]) * LB, LB);
+      Win w;
+      if (isc) w = dim_table_gen<MT>(P, i, mu[i], S.tab + (P.toff[i] + c * P.L[i]) * LB, LB, isc[i]);
+      else w = dim_table<MT>(P, i, mu[i], S.tab + (P.toff[i] + c * P.L[i]) * LB, LB);
       S.org[(P.ooff[i] + c) * LB] = w.o;
       if constexpr (TAIL) {
         double wm, gm;
-        win_grid_mass(P, i, w, wm, gm);
+        if (isc) win_grid_mass_gen(P, i, w, wm, gm, mu[i], isc[i]);
+        else win_grid_mass(P, i, w, wm, gm);
         S.wg[(2 * (P.ooff[i] + c)) * LB] = wm;
         S.wg[(2 * (P.ooff[i] + c) + 1) * LB] = gm;
       }
@@ -384,7 +621,8 @@ __device__ __forceinline__ void build_cached(const DevProblem& P, const typename
 
 // Tables of the current input: table offsets toff[] and window base index;
 // rebuilds uncached tables whose mean changed.  TAIL: returns the row's
-// FP64 tail (grid mass - kept-window mass).
+// FP64 tail (grid mass - kept-window mass).  isc: the state's inverse noise
+// scales, or nullptr for code that runs additive normal noise only.
 template <int KIND, int N, class MT, bool TAIL, int LB>
 struct RowState {
   double prev[N];
@@ -395,7 +633,7 @@ struct RowState {
     for (int i = 0; i < N; ++i) prev[i] = __builtin_nan("");
   }
   __device__ __forceinline__ int64_t prepare(const DevProblem& P, const InputWalk& iw, const double* mu,
-                                             const LaneLds<MT>& S, int* toff, double& tail) {
+                                             const double* isc, const LaneLds<MT>& S, int* toff, double& tail) {
     int64_t base = 0;
     double win = 1.0, grid = 1.0;
 #pragma unroll
@@ -411,10 +649,15 @@ struct RowState {
         }
       } else {
         if (mu[i] != prev[i]) {
-          const Win w = dim_table<MT>(P, i, mu[i], S.tab + P.toff[i] * LB, LB);
+          Win w;
+          if (isc) w = dim_table_gen<MT>(P, i, mu[i], S.tab + P.toff[i] * LB, LB, isc[i]);
+          else w = dim_table<MT>(P, i, mu[i], S.tab + P.toff[i] * LB, LB);
           o[i] = w.o;
           prev[i] = mu[i];
-          if constexpr (TAIL) win_grid_mass(P, i, w, wmem[i], gmem[i]);
+          if constexpr (TAIL) {
+            if (isc) win_grid_mass_gen(P, i, w, wmem[i], gmem[i], mu[i], isc[i]);
+            else win_grid_mass(P, i, w, wmem[i], gmem[i]);
+          }
         }
         toff[i] = P.toff[i];
         oi = o[i];

@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fixed(DevProblem P, const V
       state_centre<N>(P, s, x);
       typename Dyn<KIND, N>::State st;
       Dyn<KIND, N>::prep(P, x, st);
-      build_cached<KIND, N, MT, TAIL, FIX_BLOCK>(P, st, x, S);
+      build_cached<KIND, N, MT, TAIL, FIX_BLOCK>(P, st, x, nullptr, S);
       const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
       FixedRow<SH, MT> R;
 #pragma unroll
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fac(DevProblem P, const VI*
       state_centre<N>(P, s, x);
       typename Dyn<KIND, N>::State st;
       Dyn<KIND, N>::prep(P, x, st);
-      build_cached<KIND, N, MT, TAIL, FIX_BLOCK>(P, st, x, S);
+      build_cached<KIND, N, MT, TAIL, FIX_BLOCK>(P, st, x, nullptr, S);
       const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
       const int fd = P.m - 1;                    // the fast digit
       const int nf = P.ucount[fd];

@@ -18,11 +18,15 @@
 //   k_build       stored mode: rows of T written once (Alg. 2)
 //   k_sweep_stored one Bellman step streaming the stored rows
 //   k_copy_out    terminal vector to the FP64 output (T_d = 0)
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 
 #include "amy_device.hpp"
 #include "amy_group.hpp"
+#ifndef __HIPCC_RTC__
 #include "amy_kernels.hpp"
+#endif
 
 #define LANE_BLOCK 64
 
@@ -94,7 +98,9 @@ __device__ __forceinline__ void wave_max_to(double tmax, unsigned long long* tai
 // P_mu(grid box) - P_mu(kept window), FP64.
 // tail_state: the max over the inputs of state s's row tails (0 for states
 // off the free set and past the grid).
-template <int KIND, int N>
+// GEN: the code also takes the other noise models and multiplicative noise
+// (false for launches that hold only additive normal noise).
+template <int KIND, int N, bool GEN = true>
 __device__ __forceinline__ double tail_state(const DevProblem& P, uint32_t s, const uint8_t* __restrict__ label) {
   double tmax = 0.0;
   if (s < (uint32_t)P.n_x && label[s] == LBL_FREE) {
@@ -102,18 +108,21 @@ __device__ __forceinline__ double tail_state(const DevProblem& P, uint32_t s, co
     state_centre<N>(P, s, x);
     typename Dyn<KIND, N>::State st;
     Dyn<KIND, N>::prep(P, x, st);
+    double isc[N];
+    state_isc<N>(P, x, isc);
     InputWalk iw;
     iw.reset();
-    for (int u = 0; u < P.n_u; ++u) {
+    for (int r = 0; r < P.n_rows; ++r) {
       double uv[AMY_MAXI], mu[N];
       iw.values(P, uv);
       Dyn<KIND, N>::apply(P, st, x, uv, mu);
       double grid = 1.0, win = 1.0;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        const Win w = window_1d(P, i, mu[i]);
+        const Win w = window_1d(P, i, mu[i], GEN ? isc[i] : 1.0);
         double wm, gm;
-        win_grid_mass(P, i, w, wm, gm);
+        if constexpr (GEN) win_grid_mass_gen(P, i, w, wm, gm, mu[i], isc[i]);
+        else win_grid_mass(P, i, w, wm, gm);
         grid *= gm;
         win *= wm;
       }
@@ -124,22 +133,23 @@ __device__ __forceinline__ double tail_state(const DevProblem& P, uint32_t s, co
   return tmax;
 }
 
-template <int KIND, int N>
+template <int KIND, int N, bool GEN>
 __global__ void __launch_bounds__(LANE_BLOCK) k_tail(DevProblem P, const uint8_t* __restrict__ label,
                                                      unsigned long long* __restrict__ tailmax) {
   const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
-  wave_max_to(tail_state<KIND, N>(P, s, label), tailmax);
+  wave_max_to(tail_state<KIND, N, GEN>(P, s, label), tailmax);
 }
 
 // ------------------------------------------------------------- OTF sweep
 
-// One Bellman step k: Vout[x] = max_u sum_window T(.|x,u) Vin, policy = argmax.
+// One Bellman step k: Vout[x] = max_u min_w sum_window T(.|x,u,w) Vin, policy =
+// the maximising input (Alg. 4; without a disturbance n_w = 1).
 // Vin / Vout hold extended values (1 on T\A, 0 on A and outside S), so the
 // reach / reach-avoid T0 term of Alg. 4 is the window mass on target cells.
 // TAIL (first step only): also the FP64 max row tail into *tailmax.
 // The sweep of one state s (one lane); the whole wave must call it (the tail
 // pass ends in a wave reduction).
-template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, bool GEN = true>
 __device__ __forceinline__ void sweep_tile(const DevProblem& P, uint32_t s, const VI* __restrict__ Vin,
                                            VO* __restrict__ Vout, const uint8_t* __restrict__ label,
                                            int16_t* __restrict__ pol, unsigned long long* __restrict__ tailmax,
@@ -156,25 +166,33 @@ __device__ __forceinline__ void sweep_tile(const DevProblem& P, uint32_t s, cons
       state_centre<N>(P, s, x);
       typename Dyn<KIND, N>::State st;
       Dyn<KIND, N>::prep(P, x, st);
-      build_cached<KIND, N, MT, TAIL, LANE_BLOCK>(P, st, x, S);
+      double iscv[N];
+      state_isc<N>(P, x, iscv);
+      const double* isc = GEN ? iscv : nullptr;
+      build_cached<KIND, N, MT, TAIL, LANE_BLOCK>(P, st, x, isc, S);
       RowState<KIND, N, MT, TAIL, LANE_BLOCK> rs;
       rs.reset();
       InputWalk iw;
       iw.reset();
-      AT best = AT(-1);
-      int arg = 0;
-      for (int u = 0; u < P.n_u; ++u) {
+      AT best = AT(-1), qmin = AT(0);
+      int arg = 0, wd = 0;
+      for (int r = 0; r < P.n_rows; ++r) {
         double uv[AMY_MAXI], mu[N];
         iw.values(P, uv);
         Dyn<KIND, N>::apply(P, st, x, uv, mu);
         int toff[N];
         double tail;
-        const int64_t base = rs.prepare(P, iw, mu, S, toff, tail);
+        const int64_t base = rs.prepare(P, iw, mu, isc, S, toff, tail);
         if constexpr (TAIL) tmax = fmax(tmax, tail);
         const AT q = contract<0, N, MT, AT, VI, COMP>(P, S.tab, LANE_BLOCK, toff, Vin, base);
-        if (q > best) {
-          best = q;
-          arg = u;
+        // the disturbance minimises first (rows of one input are consecutive)
+        qmin = (wd == 0 || q < qmin) ? q : qmin;
+        if (++wd == P.n_w) {
+          wd = 0;
+          if (qmin > best) {
+            best = qmin;
+            arg = r / P.n_w;
+          }
         }
         iw.next(P);
       }
@@ -185,7 +203,86 @@ __device__ __forceinline__ void sweep_tile(const DevProblem& P, uint32_t s, cons
   if constexpr (TAIL) wave_max_to(tmax, tailmax);
 }
 
+// One wavefront per state (INPUTS variant): lane l takes the state's inputs
+// l, l + 64, ...; each input's rows (all disturbance points) run in the lane
+// with the same per-row code as sweep_tile, so every row sum has the same
+// bits.  The lanes' (value, input) pairs then meet in a butterfly that keeps
+// the larger value and, on equal values, the lower input: the lowest
+// maximising input, as the sequential walk finds it.  No table caching
+// (every lane's tables follow its own rows).
 template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+__device__ __forceinline__ void sweep_inputs(const DevProblem& P, uint32_t s, const VI* __restrict__ Vin,
+                                             VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                             int16_t* __restrict__ pol, unsigned long long* __restrict__ tailmax,
+                                             unsigned char* smem) {
+  const int lane = threadIdx.x & 63;
+  const LaneLds<MT> S(P, smem, lane);
+  double tmax = 0.0;
+  const uint8_t lb = label[s];
+  if (lb != LBL_FREE) {
+    if (lane == 0) {
+      Vout[s] = (lb == LBL_ONE) ? VO(1) : VO(0);
+      if (pol) pol[s] = -1;
+    }
+    return;
+  }
+  double x[N];
+  state_centre<N>(P, s, x);
+  typename Dyn<KIND, N>::State st;
+  Dyn<KIND, N>::prep(P, x, st);
+  RowState<KIND, N, MT, TAIL, LANE_BLOCK> rs;
+  rs.reset();
+  InputWalk iw;
+  AT best = AT(-1);
+  int arg = 0x7fffffff;
+  for (int u = lane; u < P.n_u; u += 64) {
+    iw.set_input(P, u);
+    AT qmin = AT(0);
+    for (int w = 0; w < P.n_w; ++w) {
+      double uv[AMY_MAXI], mu[N];
+      iw.values(P, uv);
+      Dyn<KIND, N>::apply(P, st, x, uv, mu);
+      int toff[N];
+      double tail;
+      const int64_t base = rs.prepare(P, iw, mu, nullptr, S, toff, tail);
+      if constexpr (TAIL) tmax = fmax(tmax, tail);
+      const AT q = contract<0, N, MT, AT, VI, COMP>(P, S.tab, LANE_BLOCK, toff, Vin, base);
+      qmin = (w == 0 || q < qmin) ? q : qmin;
+      iw.next(P);
+    }
+    if (qmin > best) {
+      best = qmin;
+      arg = u;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const AT ob = __shfl_xor(best, off);
+    const int oa = __shfl_xor(arg, off);
+    if (ob > best || (ob == best && oa < arg)) {
+      best = ob;
+      arg = oa;
+    }
+  }
+  if (lane == 0) {
+    Vout[s] = VO(best);
+    if (pol) pol[s] = (int16_t)arg;
+  }
+  if constexpr (TAIL) wave_max_to(tmax, tailmax);
+}
+
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
+__global__ void __launch_bounds__(LANE_BLOCK) k_sweep_inputs(DevProblem P, const VI* __restrict__ Vin,
+                                                             VO* __restrict__ Vout,
+                                                             const uint8_t* __restrict__ label,
+                                                             int16_t* __restrict__ pol,
+                                                             unsigned long long* __restrict__ tailmax) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  sweep_inputs<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, xcd_block(blockIdx.x, gridDim.x), Vin, Vout, label, pol,
+                                                    tailmax, smem);
+}
+
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, bool GEN>
 __global__ void __launch_bounds__(LANE_BLOCK) k_sweep_otf(DevProblem P, const VI* __restrict__ Vin,
                                                           VO* __restrict__ Vout,
                                                           const uint8_t* __restrict__ label,
@@ -193,25 +290,26 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_sweep_otf(DevProblem P, const VI
                                                           unsigned long long* __restrict__ tailmax) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * LANE_BLOCK + threadIdx.x;
-  sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL>(P, s, Vin, Vout, label, pol, tailmax, smem);
+  sweep_tile<KIND, N, MT, AT, VI, VO, COMP, TAIL, GEN>(P, s, Vin, Vout, label, pol, tailmax, smem);
 }
 
-template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G>
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G, bool GEN>
 __global__ void __launch_bounds__(LANE_BLOCK) k_sweep_group(DevProblem P, const VI* __restrict__ Vin,
                                                             VO* __restrict__ Vout,
                                                             const uint8_t* __restrict__ label,
                                                             int16_t* __restrict__ pol,
                                                             unsigned long long* __restrict__ tailmax) {
   extern __shared__ __align__(16) unsigned char smem[];
-  sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G>(P, xcd_block(blockIdx.x, gridDim.x), Vin, Vout, label, pol,
+  sweep_group<KIND, N, MT, AT, VI, VO, COMP, TAIL, G, GEN>(P, xcd_block(blockIdx.x, gridDim.x), Vin, Vout, label, pol,
                                                       tailmax, smem);
 }
 
 // --------------------------------------------------------------- stored
 
-// Stored row layout: rows grouped by 64-state tiles; within a tile, input u
-// and slot w, the 64 states are contiguous:
-//   T[((tile * n_u + u) * W + w) * 64 + lane],  org[(tile * n_u + u) * 64 + lane].
+// Stored row layout: rows grouped by 64-state tiles; within a tile, row r
+// (input and disturbance, r = u n_w + w) and slot k, the 64 states are
+// contiguous:
+//   T[((tile * n_rows + r) * W + k) * 64 + lane],  org[(tile * n_rows + r) * 64 + lane].
 template <int D, int N, class MT>
 __device__ __forceinline__ void write_row(const DevProblem& P, const MT* __restrict__ t, const int* toff,
                                           MT pre, MT* __restrict__& out) {
@@ -231,10 +329,10 @@ __device__ __forceinline__ void write_row(const DevProblem& P, const MT* __restr
 // Flat V offsets of the W window slots (row-major, last dimension fastest),
 // stored after the rows' origins: the same for every row.
 __device__ __forceinline__ const int32_t* slot_offsets(const DevProblem& P, const int32_t* org) {
-  return org + (int64_t)((P.n_x + LANE_BLOCK - 1) / LANE_BLOCK) * LANE_BLOCK * P.n_u;
+  return org + (int64_t)((P.n_x + LANE_BLOCK - 1) / LANE_BLOCK) * LANE_BLOCK * P.n_rows;
 }
 
-template <int KIND, int N, class MT, bool TAIL>
+template <int KIND, int N, class MT, bool TAIL, bool GEN>
 __global__ void __launch_bounds__(LANE_BLOCK) k_build(DevProblem P, const uint8_t* __restrict__ label,
                                                       MT* __restrict__ T, int32_t* __restrict__ org,
                                                       unsigned long long* __restrict__ tailmax) {
@@ -259,21 +357,24 @@ __global__ void __launch_bounds__(LANE_BLOCK) k_build(DevProblem P, const uint8_
     state_centre<N>(P, s, x);
     typename Dyn<KIND, N>::State st;
     Dyn<KIND, N>::prep(P, x, st);
-    build_cached<KIND, N, MT, TAIL, LANE_BLOCK>(P, st, x, S);
+    double iscv[N];
+    state_isc<N>(P, x, iscv);
+    const double* isc = GEN ? iscv : nullptr;
+    build_cached<KIND, N, MT, TAIL, LANE_BLOCK>(P, st, x, isc, S);
     RowState<KIND, N, MT, TAIL, LANE_BLOCK> rs;
     rs.reset();
     InputWalk iw;
     iw.reset();
     const int64_t tile = s / LANE_BLOCK, lane = s % LANE_BLOCK;
-    for (int u = 0; u < P.n_u; ++u) {
+    for (int r = 0; r < P.n_rows; ++r) {
       double uv[AMY_MAXI], mu[N];
       iw.values(P, uv);
       Dyn<KIND, N>::apply(P, st, x, uv, mu);
       int toff[N];
       double tail;
-      const int64_t base = rs.prepare(P, iw, mu, S, toff, tail);
+      const int64_t base = rs.prepare(P, iw, mu, isc, S, toff, tail);
       if constexpr (TAIL) tmax = fmax(tmax, tail);
-      const int64_t rt = tile * P.n_u + u;
+      const int64_t rt = tile * P.n_rows + r;
       MT* out = T + rt * (int64_t)P.W * LANE_BLOCK + lane;
       write_row<0, N, MT>(P, S.tab, toff, MT(1), out);
       org[rt * LANE_BLOCK + lane] = (int32_t)base;
@@ -339,16 +440,20 @@ __device__ __forceinline__ void stored_tile(const DevProblem& P, uint32_t s, con
   const int32_t* offs = slot_offsets(P, org);
   const __amdgpu_buffer_rsrc_t vr =
       __builtin_amdgcn_make_buffer_rsrc((void*)Vin, (short)0, (int)((uint32_t)P.n_x * (uint32_t)sizeof(VI)), 0x00020000);
-  AT best = AT(-1);
-  int arg = 0;
-  for (int u = 0; u < P.n_u; ++u) {
-    const int64_t rt = tile * P.n_u + u;
+  AT best = AT(-1), qmin = AT(0);
+  int arg = 0, wd = 0;
+  for (int r = 0; r < P.n_rows; ++r) {
+    const int64_t rt = tile * P.n_rows + r;
     const MT* t = T + rt * (int64_t)P.W * LANE_BLOCK + lane;
     const uint32_t voff = (uint32_t)org[rt * LANE_BLOCK + lane] * (uint32_t)sizeof(VI);
     const AT acc = stored_row<MT, AT, VI, COMP>(P.W, t, vr, voff, offs);
-    if (acc > best) {
-      best = acc;
-      arg = u;
+    qmin = (wd == 0 || acc < qmin) ? acc : qmin;
+    if (++wd == P.n_w) {
+      wd = 0;
+      if (qmin > best) {
+        best = qmin;
+        arg = r / P.n_w;
+      }
     }
   }
   Vout[s] = VO(best);
@@ -373,6 +478,7 @@ __global__ void __launch_bounds__(256) k_copy_out(int64_t n, const VT* __restric
   if (s < n) dst[s] = (double)src[s];
 }
 
+#ifndef __HIPCC_RTC__  // host launchers: not part of a run-time-compiled module
 // ============================================================ host launchers
 
 static inline unsigned lane_grid(int64_t n_x) { return (unsigned)((n_x + LANE_BLOCK - 1) / LANE_BLOCK); }
@@ -400,20 +506,45 @@ template <int KIND, int N>
 struct Launch {
   static hipError_t tail(const DevProblem& P, const uint8_t* label, unsigned long long* tailmax,
                          hipStream_t st) {
-    hipLaunchKernelGGL((k_tail<KIND, N>), dim3(lane_grid(P.n_x)), dim3(LANE_BLOCK), 0, st, P, label,
-                       tailmax);
+    if (P.noise != 0 || P.mult)
+      hipLaunchKernelGGL((k_tail<KIND, N, true>), dim3(lane_grid(P.n_x)), dim3(LANE_BLOCK), 0, st, P, label,
+                         tailmax);
+    else
+      hipLaunchKernelGGL((k_tail<KIND, N, false>), dim3(lane_grid(P.n_x)), dim3(LANE_BLOCK), 0, st, P, label,
+                         tailmax);
     return hipGetLastError();
+  }
+  // GEN instances (other noise models, multiplicative noise) are launched
+  // only for problems that need them: the others run code with no call to
+  // the general mass path
+  template <class MT, class AT, class VI, class VO, bool COMP, bool GEN>
+  static void sweep_tg(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                       unsigned long long* tailmax, hipStream_t st) {
+    const dim3 g(lane_grid(P.n_x)), b(LANE_BLOCK);
+    if (tailmax)
+      hipLaunchKernelGGL((k_sweep_otf<KIND, N, MT, AT, VI, VO, COMP, true, GEN>), g, b, P.lds_bytes_tail, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+    else
+      hipLaunchKernelGGL((k_sweep_otf<KIND, N, MT, AT, VI, VO, COMP, false, GEN>), g, b, P.lds_bytes, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+  }
+  template <class MT, class AT, class VI, class VO, bool COMP>
+  static void inputs_t(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                       unsigned long long* tailmax, hipStream_t st) {
+    const dim3 g((unsigned)P.n_x), b(LANE_BLOCK);
+    if (tailmax)
+      hipLaunchKernelGGL((k_sweep_inputs<KIND, N, MT, AT, VI, VO, COMP, true>), g, b, P.lds_bytes, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+    else
+      hipLaunchKernelGGL((k_sweep_inputs<KIND, N, MT, AT, VI, VO, COMP, false>), g, b, P.lds_bytes, st, P,
+                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
   }
   template <class MT, class AT, class VI, class VO, bool COMP>
   static void sweep_t(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
                       unsigned long long* tailmax, hipStream_t st) {
-    const dim3 g(lane_grid(P.n_x)), b(LANE_BLOCK);
-    if (tailmax)
-      hipLaunchKernelGGL((k_sweep_otf<KIND, N, MT, AT, VI, VO, COMP, true>), g, b, P.lds_bytes_tail, st, P,
-                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
-    else
-      hipLaunchKernelGGL((k_sweep_otf<KIND, N, MT, AT, VI, VO, COMP, false>), g, b, P.lds_bytes, st, P,
-                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+    if (P.variant == 6) inputs_t<MT, AT, VI, VO, COMP>(P, Vin, Vout, label, pol, tailmax, st);
+    else if (P.noise != 0 || P.mult) sweep_tg<MT, AT, VI, VO, COMP, true>(P, Vin, Vout, label, pol, tailmax, st);
+    else sweep_tg<MT, AT, VI, VO, COMP, false>(P, Vin, Vout, label, pol, tailmax, st);
   }
   static hipError_t sweep(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
                           const uint8_t* label, int16_t* pol, unsigned long long* tailmax, hipStream_t st) {
@@ -424,16 +555,22 @@ struct Launch {
     }
     return hipGetLastError();
   }
+  template <class MT, class AT, class VI, class VO, bool COMP, int G, bool GEN>
+  static void group_tg(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                       unsigned long long* tailmax, hipStream_t st) {
+    const dim3 g((unsigned)((P.n_x + (64 / G) - 1) / (64 / G))), b(LANE_BLOCK);
+    if (tailmax)
+      hipLaunchKernelGGL((k_sweep_group<KIND, N, MT, AT, VI, VO, COMP, true, G, GEN>), g, b, P.lds_bytes_group, st,
+                         P, (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+    else
+      hipLaunchKernelGGL((k_sweep_group<KIND, N, MT, AT, VI, VO, COMP, false, G, GEN>), g, b, P.lds_bytes_group, st,
+                         P, (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+  }
   template <class MT, class AT, class VI, class VO, bool COMP, int G>
   static void group_t(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
                       unsigned long long* tailmax, hipStream_t st) {
-    const dim3 g((unsigned)((P.n_x + (64 / G) - 1) / (64 / G))), b(LANE_BLOCK);
-    if (tailmax)
-      hipLaunchKernelGGL((k_sweep_group<KIND, N, MT, AT, VI, VO, COMP, true, G>), g, b, P.lds_bytes_group, st, P,
-                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
-    else
-      hipLaunchKernelGGL((k_sweep_group<KIND, N, MT, AT, VI, VO, COMP, false, G>), g, b, P.lds_bytes_group, st, P,
-                         (const VI*)Vin, (VO*)Vout, label, pol, tailmax);
+    if (P.noise != 0 || P.mult) group_tg<MT, AT, VI, VO, COMP, G, true>(P, Vin, Vout, label, pol, tailmax, st);
+    else group_tg<MT, AT, VI, VO, COMP, G, false>(P, Vin, Vout, label, pol, tailmax, st);
   }
   template <int G>
   static void group_g(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout, const uint8_t* label,
@@ -450,14 +587,21 @@ struct Launch {
     else group_g<16>(P, sk, Vin, Vout, label, pol, tailmax, st);
     return hipGetLastError();
   }
+  template <class MT, bool GEN>
+  static void build_tg(const DevProblem& P, const uint8_t* label, void* T, int32_t* org,
+                       unsigned long long* tailmax, hipStream_t st) {
+    const dim3 g(lane_grid(P.n_x)), b(LANE_BLOCK);
+    if (tailmax)
+      hipLaunchKernelGGL((k_build<KIND, N, MT, true, GEN>), g, b, P.lds_bytes_tail, st, P, label, (MT*)T, org,
+                         tailmax);
+    else
+      hipLaunchKernelGGL((k_build<KIND, N, MT, false, GEN>), g, b, P.lds_bytes, st, P, label, (MT*)T, org, tailmax);
+  }
   template <class MT>
   static void build_t(const DevProblem& P, const uint8_t* label, void* T, int32_t* org,
                       unsigned long long* tailmax, hipStream_t st) {
-    const dim3 g(lane_grid(P.n_x)), b(LANE_BLOCK);
-    if (tailmax)
-      hipLaunchKernelGGL((k_build<KIND, N, MT, true>), g, b, P.lds_bytes_tail, st, P, label, (MT*)T, org, tailmax);
-    else
-      hipLaunchKernelGGL((k_build<KIND, N, MT, false>), g, b, P.lds_bytes, st, P, label, (MT*)T, org, tailmax);
+    if (P.noise != 0 || P.mult) build_tg<MT, true>(P, label, T, org, tailmax, st);
+    else build_tg<MT, false>(P, label, T, org, tailmax, st);
   }
   static hipError_t build(const DevProblem& P, bool f64, const uint8_t* label, void* T, int32_t* org,
                           unsigned long long* tailmax, hipStream_t st) {
@@ -489,3 +633,5 @@ static hipError_t sweep_stored_n(const DevProblem& P, SweepKind sk, const void* 
   return hipGetLastError();
 }
 
+
+#endif  // __HIPCC_RTC__

@@ -13,10 +13,13 @@
 
 // Mass of window slot k of dimension i (both edges evaluated here; the same
 // edge values, clamps and differencing as dim_table).
-template <class MT>
-__device__ __forceinline__ MT slot_mass(const DevProblem& P, int i, const Win& w, int k) {
-  const double z0 = edge_z(P, i, w, min(max(w.o + k, w.jlo), w.b));
-  const double z1 = edge_z(P, i, w, min(max(w.o + k + 1, w.jlo), w.b));
+template <class MT, bool GEN>
+__device__ __forceinline__ MT slot_mass(const DevProblem& P, int i, const Win& w, int k, double mu, double isc) {
+  const int e0 = min(max(w.o + k, w.jlo), w.b), e1 = min(max(w.o + k + 1, w.jlo), w.b);
+  if constexpr (GEN)
+    if (P.noise != 0 || P.mult) return MT(general_mass(P, i, w, e0, e1, mu, isc));
+  const double z0 = edge_z(P, i, w, e0);
+  const double z1 = edge_z(P, i, w, e1);
   return mass_of(z0, ec_of(z0, MT()), z1, ec_of(z1, MT()));
 }
 
@@ -50,7 +53,7 @@ __device__ __forceinline__ AT gsum(const DevProblem& P, int nout, const MT* __re
   }
 }
 
-template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G>
+template <int KIND, int N, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int G, bool GEN = true>
 __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, const VI* __restrict__ Vin,
                                             VO* __restrict__ Vout, const uint8_t* __restrict__ label,
                                             int16_t* __restrict__ pol, unsigned long long* __restrict__ tailmax,
@@ -70,6 +73,8 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
   state_centre<N>(P, inside ? s : 0u, x);
   typename Dyn<KIND, N>::State st;
   Dyn<KIND, N>::prep(P, x, st);
+  double isc[N];
+  state_isc<N>(P, x, isc);
   double prev[N];
   int o[N];
   double wmem[TAIL ? N : 1], gmem[TAIL ? N : 1];
@@ -86,10 +91,10 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
     if (i >= nout) ls *= P.L[i];
   InputWalk iw;
   iw.reset();
-  AT best = AT(-1);
-  int arg = 0;
+  AT best = AT(-1), qmin = AT(0);
+  int arg = 0, wd = 0;
   double tmax = 0.0;
-  for (int u = 0; u < P.n_u; ++u) {
+  for (int r = 0; r < P.n_rows; ++r) {
     double uv[AMY_MAXI], mu[N];
     iw.values(P, uv);
     Dyn<KIND, N>::apply(P, st, x, uv, mu);
@@ -97,12 +102,15 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       if (mu[i] != prev[i]) {
-        const Win w = window_1d(P, i, mu[i]);
+        const Win w = window_1d(P, i, mu[i], GEN ? isc[i] : 1.0);
         o[i] = w.o;
         prev[i] = mu[i];
         if (active)
-          for (int k = gl; k < P.L[i]; k += G) tab[P.goff[i] + k] = slot_mass<MT>(P, i, w, k);
-        if constexpr (TAIL) win_grid_mass(P, i, w, wmem[i], gmem[i]);
+          for (int k = gl; k < P.L[i]; k += G) tab[P.goff[i] + k] = slot_mass<MT, GEN>(P, i, w, k, mu[i], isc[i]);
+        if constexpr (TAIL) {
+          if constexpr (GEN) win_grid_mass_gen(P, i, w, wmem[i], gmem[i], mu[i], isc[i]);
+          else win_grid_mass(P, i, w, wmem[i], gmem[i]);
+        }
       }
       if constexpr (TAIL) {
         win *= wmem[i];
@@ -118,12 +126,12 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
       for (int j = gl; j < ls; j += G) {
         int kin[N];
         AT mi = AT(1);
-        int r = j;
+        int rr = j;
 #pragma unroll
         for (int i = N - 1; i >= 0; --i) {
           if (i >= nout) {
-            const int k = r % P.L[i];
-            r /= P.L[i];
+            const int k = rr % P.L[i];
+            rr /= P.L[i];
             kin[i] = k;
           } else {
             kin[i] = 0;
@@ -146,9 +154,13 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
     // sum of the group's partials (butterfly inside each group of G lanes)
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (acc > best) {
-      best = acc;
-      arg = u;
+    qmin = (wd == 0 || acc < qmin) ? acc : qmin;
+    if (++wd == P.n_w) {
+      wd = 0;
+      if (qmin > best) {
+        best = qmin;
+        arg = r / P.n_w;
+      }
     }
     if constexpr (TAIL)
       if (active) tmax = fmax(tmax, grid - win);

@@ -32,6 +32,55 @@ amy_status amy_hip_fail(hipError_t e, const char* what) {
 extern "C" const char* amy_last_error(void) { return g_err.c_str(); }
 extern "C" const char* amy_version(void) { return "amytiss-hip 0.1 (gfx950)"; }
 
+// ------------------------------------------------------- quantisation
+
+// The paper's quantisation convention: points lb + j q, both ends of
+// [lb, ub] included; as cells lo = lb - q/2, h = q.
+static amy_status quant_count(const double* lb, const double* ub, const double* q, int k, int32_t* count) {
+  if (!isfinite(lb[k]) || !isfinite(ub[k]) || !isfinite(q[k]))
+    return amy_fail(AMY_E_INVALID, "quantisation of dimension %d not finite", k);
+  if (!(q[k] > 0)) return amy_fail(AMY_E_INVALID, "quantisation parameter q[%d] <= 0", k);
+  if (ub[k] < lb[k]) return amy_fail(AMY_E_INVALID, "ub[%d] < lb[%d]", k, k);
+  const double c = floor((ub[k] - lb[k]) / q[k] + 1e-9) + 1.0;
+  if (c > 2147483647.0) return amy_fail(AMY_E_INVALID, "dimension %d has more than 2^31 - 1 points", k);
+  *count = (int32_t)c;
+  return AMY_OK;
+}
+
+extern "C" amy_status amy_grid_from_quantization(int32_t n, const double* lb, const double* ub, const double* q,
+                                                 amy_grid* out) {
+  if (n < 1 || n > AMY_MAX_DIM) return amy_fail(AMY_E_INVALID, "n=%d not in [1,%d]", n, AMY_MAX_DIM);
+  if (!lb || !ub || !q || !out) return amy_fail(AMY_E_INVALID, "NULL argument");
+  amy_grid g;
+  memset(&g, 0, sizeof g);
+  g.n = n;
+  for (int i = 0; i < n; ++i) {
+    const amy_status st = quant_count(lb, ub, q, i, &g.count[i]);
+    if (st != AMY_OK) return st;
+    g.lo[i] = lb[i] - q[i] / 2.0;
+    g.h[i] = q[i];
+  }
+  *out = g;
+  return AMY_OK;
+}
+
+extern "C" amy_status amy_inputs_from_quantization(int32_t m, const double* lb, const double* ub, const double* q,
+                                                   amy_inputs* out) {
+  if (m < 1 || m > AMY_MAX_IN) return amy_fail(AMY_E_INVALID, "m=%d not in [1,%d]", m, AMY_MAX_IN);
+  if (!lb || !ub || !q || !out) return amy_fail(AMY_E_INVALID, "NULL argument");
+  amy_inputs u;
+  memset(&u, 0, sizeof u);
+  u.m = m;
+  for (int k = 0; k < m; ++k) {
+    const amy_status st = quant_count(lb, ub, q, k, &u.count[k]);
+    if (st != AMY_OK) return st;
+    u.lo[k] = lb[k];
+    u.hi[k] = lb[k] + (double)(u.count[k] - 1) * q[k];
+  }
+  *out = u;
+  return AMY_OK;
+}
+
 // ---------------------------------------------------------------- planning
 
 static const double SQRT_2PI = 2.5066282746310002;
@@ -47,12 +96,50 @@ static double xstar_of(double var, double cutoff) {
 static int expected_params(const amy_problem* p) {
   const int n = p->grid.n, m = p->inputs.m;
   switch (p->dyn.kind) {
-    case AMY_DYN_AFFINE: return n * n + n * m + n;
+    case AMY_DYN_AFFINE: return n * n + n * m + n + n * p->dist.p;
     case AMY_DYN_UNICYCLE: return 1;
     case AMY_DYN_ROOM: return 5;
     case AMY_DYN_VEHICLE7: return 11;
+    case AMY_DYN_ROBOT: return 1;
+    case AMY_DYN_USER: return (p->dyn.n_params >= 0 && p->dyn.n_params <= AMY_MAX_PARAMS) ? p->dyn.n_params : -1;
   }
   return -1;
+}
+
+// Exponential noise: the support [0, inf) cut where the density rate e^{-rate t}
+// falls to the cutoff; INFINITY without a cut.
+static double exp_cut(double rate, double cutoff) {
+  if (cutoff <= 0.0) return INFINITY;
+  return log(rate / cutoff) / rate;
+}
+
+static amy_status validate_noise(const amy_problem* p) {
+  const amy_noise& z = p->noise;
+  const int n = p->grid.n;
+  if (z.kind < AMY_NOISE_NORMAL || z.kind > AMY_NOISE_BETA) return amy_fail(AMY_E_INVALID, "bad noise kind %d", z.kind);
+  if (z.window != AMY_WINDOW_CENTRE && z.window != AMY_WINDOW_INTERSECT)
+    return amy_fail(AMY_E_INVALID, "bad window rule %d", z.window);
+  if (z.multiplicative != 0 && z.multiplicative != 1) return amy_fail(AMY_E_INVALID, "multiplicative must be 0 or 1");
+  if (z.kind != AMY_NOISE_NORMAL && (z.multiplicative || z.window != AMY_WINDOW_CENTRE))
+    return amy_fail(AMY_E_INVALID, "window rule and multiplicative noise apply to normal noise only");
+  for (int i = 0; i < n; ++i) {
+    switch (z.kind) {
+      case AMY_NOISE_UNIFORM:
+      case AMY_NOISE_BETA:
+        if (!isfinite(z.a[i]) || !isfinite(z.b[i]) || !(z.b[i] > z.a[i]))
+          return amy_fail(AMY_E_INVALID, "noise support [a, b] of dimension %d is empty or not finite", i);
+        if (z.kind == AMY_NOISE_BETA && (!(z.alpha[i] >= 1.0) || !(z.beta[i] >= 1.0) || !isfinite(z.alpha[i]) ||
+                                         !isfinite(z.beta[i]) || z.alpha[i] > 1e6 || z.beta[i] > 1e6))
+          return amy_fail(AMY_E_INVALID, "beta shapes of dimension %d must lie in [1, 1e6]", i);
+        break;
+      case AMY_NOISE_EXPONENTIAL:
+        if (!(z.a[i] > 0.0) || !isfinite(z.a[i])) return amy_fail(AMY_E_INVALID, "exponential rate a[%d] <= 0", i);
+        if (p->cutoff > 0.0 && !(p->cutoff < z.a[i]))
+          return amy_fail(AMY_E_INVALID, "cutoff %g is at or above the peak density of dimension %d", p->cutoff, i);
+        break;
+    }
+  }
+  return AMY_OK;
 }
 
 amy_status amy_validate(const amy_problem* p) {
@@ -65,7 +152,7 @@ amy_status amy_validate(const amy_problem* p) {
     if (p->grid.count[i] < 1) return amy_fail(AMY_E_INVALID, "grid.count[%d]=%d < 1", i, p->grid.count[i]);
     if (!(p->grid.h[i] > 0) || !isfinite(p->grid.h[i])) return amy_fail(AMY_E_INVALID, "grid.h[%d] <= 0", i);
     if (!isfinite(p->grid.lo[i])) return amy_fail(AMY_E_INVALID, "grid.lo[%d] not finite", i);
-    if (!(p->noise_var[i] > 0) || !isfinite(p->noise_var[i]))
+    if (p->noise.kind == AMY_NOISE_NORMAL && (!(p->noise_var[i] > 0) || !isfinite(p->noise_var[i])))
       return amy_fail(AMY_E_INVALID, "noise_var[%d] <= 0", i);
     nx *= p->grid.count[i];
   }
@@ -80,8 +167,27 @@ amy_status amy_validate(const amy_problem* p) {
     nu *= p->inputs.count[k];
   }
   if (nu > 32767) return amy_fail(AMY_E_UNSUPPORTED, "n_u=%.0f > 32767 (int16 policy)", nu);
+  const int pd = p->dist.p;
+  if (pd < 0 || m + pd > AMY_MAX_IN)
+    return amy_fail(AMY_E_INVALID, "dist.p=%d: inputs plus disturbance dimensions exceed %d", pd, AMY_MAX_IN);
+  double nw = 1;
+  for (int l = 0; l < pd; ++l) {
+    if (p->dist.count[l] < 1) return amy_fail(AMY_E_INVALID, "dist.count[%d] < 1", l);
+    if (!isfinite(p->dist.lo[l]) || !isfinite(p->dist.hi[l]))
+      return amy_fail(AMY_E_INVALID, "disturbance bounds of dim %d not finite", l);
+    if (p->dist.count[l] > 1 && !(p->dist.hi[l] >= p->dist.lo[l]))
+      return amy_fail(AMY_E_INVALID, "dist.hi[%d] < dist.lo[%d]", l, l);
+    nw *= p->dist.count[l];
+  }
+  if (nu * nw > 1e6) return amy_fail(AMY_E_UNSUPPORTED, "%.0f (input, disturbance) rows per state > 1e6", nu * nw);
+  if (pd > 0 && p->dyn.kind != AMY_DYN_AFFINE && p->dyn.kind != AMY_DYN_ROBOT && p->dyn.kind != AMY_DYN_USER)
+    return amy_fail(AMY_E_INVALID, "dynamics kind %d takes no disturbance", p->dyn.kind);
+  {
+    const amy_status sn = validate_noise(p);
+    if (sn != AMY_OK) return sn;
+  }
   if (!(p->cutoff >= 0) || !isfinite(p->cutoff)) return amy_fail(AMY_E_INVALID, "cutoff < 0");
-  if (p->cutoff > 0) {
+  if (p->cutoff > 0 && p->noise.kind == AMY_NOISE_NORMAL && !p->noise.multiplicative) {
     for (int i = 0; i < n; ++i) {
       const double t = (p->cutoff * sqrt(p->noise_var[i])) * SQRT_2PI;
       if (!(t < 1.0))
@@ -93,7 +199,7 @@ amy_status amy_validate(const amy_problem* p) {
   if (p->spec < AMY_SAFETY || p->spec > AMY_REACH_AVOID) return amy_fail(AMY_E_INVALID, "bad spec");
   if (p->mode < AMY_MODE_AUTO || p->mode > AMY_MODE_OTF) return amy_fail(AMY_E_INVALID, "bad mode");
   if (p->precision != AMY_FP64 && p->precision != AMY_FP32) return amy_fail(AMY_E_INVALID, "bad precision");
-  if (p->variant < AMY_VARIANT_AUTO || p->variant > AMY_VARIANT_FACTORED) return amy_fail(AMY_E_INVALID, "bad variant");
+  if (p->variant < AMY_VARIANT_AUTO || p->variant > AMY_VARIANT_INPUTS) return amy_fail(AMY_E_INVALID, "bad variant");
   const int ep = expected_params(p);
   if (ep < 0) return amy_fail(AMY_E_INVALID, "bad dynamics kind %d", p->dyn.kind);
   if (p->dyn.kind == AMY_DYN_UNICYCLE && (n != 3 || m != 2))
@@ -102,6 +208,8 @@ amy_status amy_validate(const amy_problem* p) {
     return amy_fail(AMY_E_INVALID, "vehicle7 needs n=7, m=2");
   if (p->dyn.kind == AMY_DYN_ROOM && !(m == 1 || m == n))
     return amy_fail(AMY_E_INVALID, "room needs m=1 (shared heater) or m=n");
+  if (p->dyn.kind == AMY_DYN_ROBOT && (n != 2 || m != 2 || pd > 1))
+    return amy_fail(AMY_E_INVALID, "robot needs n=2, m=2 and at most one disturbance dimension");
   if (p->dyn.n_params != ep)
     return amy_fail(AMY_E_INVALID, "dynamics needs %d params, got %d", ep, p->dyn.n_params);
   for (int k = 0; k < p->dyn.n_params; ++k)
@@ -109,18 +217,23 @@ amy_status amy_validate(const amy_problem* p) {
   return AMY_OK;
 }
 
-// Input dimensions each state dimension's mean depends on (bit k = input
-// dimension k), from the structure of each dynamics family.
+// Input-walk digits each state dimension's mean depends on (bit k = digit
+// k: the inputs, then the disturbance dimensions), from the structure of
+// each dynamics family.
 static uint32_t dep_mask(const amy_problem* p, int i) {
-  const int n = p->grid.n, m = p->inputs.m;
-  uint32_t all = (1u << m) - 1u;
+  const int n = p->grid.n, m = p->inputs.m, pd = p->dist.p;
+  uint32_t all = (1u << (m + pd)) - 1u;
   switch (p->dyn.kind) {
     case AMY_DYN_AFFINE: {
       uint32_t d = 0;
       for (int k = 0; k < m; ++k)
         if (p->dyn.params[n * n + i * m + k] != 0.0) d |= 1u << k;
+      for (int l = 0; l < pd; ++l)
+        if (p->dyn.params[n * n + n * m + n + i * pd + l] != 0.0) d |= 1u << (m + l);
       return d;
     }
+    case AMY_DYN_ROBOT: return all;
+    case AMY_DYN_USER: return all;
     case AMY_DYN_UNICYCLE: return i < 2 ? 1u : 2u;  // x, y: speed; theta: turn rate
     case AMY_DYN_ROOM: return m == 1 ? 1u : (1u << i);
     case AMY_DYN_VEHICLE7: {
@@ -195,9 +308,10 @@ static bool plan_memo(const amy_problem* p, DevProblem& D) {
 
 // Which dimensions get all their tables built once per state (the others
 // are rebuilt in the input loop when their mean changes), and the LDS layout.
-static amy_status plan_tables(const amy_problem* p, Plan* pl) {
+// no_cache: none are (the INPUTS variant, whose lanes walk different inputs).
+static amy_status plan_tables(const amy_problem* p, Plan* pl, bool no_cache = false) {
   DevProblem& D = pl->dev;
-  const int n = D.n, m = D.m;
+  const int n = D.n, m = D.nd;  // digits of the input walk (inputs, then disturbance)
   const int msz = pl->f64 ? 8 : 4;
   int runs[AMY_MAX_DIM], C[AMY_MAX_DIM];
   uint32_t dep[AMY_MAX_DIM];
@@ -230,7 +344,7 @@ static amy_status plan_tables(const amy_problem* p, Plan* pl) {
     return amy_fail(AMY_E_UNSUPPORTED, "window tables need %lld B of LDS per 64 lanes (> %d)",
                     (long long)bytes(true), LDS_BUDGET);
   // greedy: cache the dimension saving the most edge evaluations per byte
-  for (;;) {
+  for (; !no_cache;) {
     int best = -1;
     double best_gain = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -314,7 +428,13 @@ void amy_make_plan(const amy_problem* p, Plan* pl) {
   D.m = m;
   D.kind = p->dyn.kind;
   D.spec = p->spec;
-  D.nocut = (p->cutoff == 0.0);
+  const amy_noise& nz = p->noise;
+  D.noise = nz.kind;
+  D.wrule = (nz.kind == AMY_NOISE_NORMAL) ? nz.window : AMY_WINDOW_INTERSECT;
+  D.mult = nz.multiplicative;
+  // multiplicative noise disables the cut (Sec. 6.2); bounded supports are
+  // cut by their support whatever gamma is
+  D.nocut = (nz.kind == AMY_NOISE_NORMAL && (p->cutoff == 0.0 || nz.multiplicative));
   int64_t nx = 1;
   for (int i = n - 1; i >= 0; --i) {
     D.stride[i] = nx;
@@ -327,18 +447,47 @@ void amy_make_plan(const amy_problem* p, Plan* pl) {
     D.lo[i] = p->grid.lo[i];
     D.h[i] = p->grid.h[i];
     D.inv_h[i] = 1.0 / p->grid.h[i];
-    const double sigma = sqrt(p->noise_var[i]);
-    D.inv_sigma[i] = 1.0 / sigma;
+    // standardised edge coordinate z = (edge - mu) inv_sigma and the cutting
+    // interval [mu + zl, mu + zh] of each noise model
+    double zl = -INFINITY, zh = INFINITY;
+    switch (nz.kind) {
+      case AMY_NOISE_UNIFORM:
+      case AMY_NOISE_BETA:
+        D.inv_sigma[i] = 1.0 / (nz.b[i] - nz.a[i]);
+        D.zoff[i] = nz.a[i] * D.inv_sigma[i];
+        D.balpha[i] = nz.alpha[i];
+        D.bbeta[i] = nz.beta[i];
+        zl = nz.a[i];
+        zh = nz.b[i];
+        break;
+      case AMY_NOISE_EXPONENTIAL:
+        D.inv_sigma[i] = nz.a[i];
+        zl = 0.0;
+        zh = exp_cut(nz.a[i], p->cutoff);
+        break;
+      default: {
+        const double sigma = sqrt(p->noise_var[i]);
+        D.inv_sigma[i] = 1.0 / sigma;
+        if (!D.nocut) {
+          const double xs = xstar_of(p->noise_var[i], p->cutoff);
+          zl = -xs;
+          zh = xs;
+        }
+      }
+    }
     D.hs[i] = p->grid.h[i] * D.inv_sigma[i];
     int L = p->grid.count[i];
+    D.xstar[i] = INFINITY;
     if (!D.nocut) {
-      D.xstar[i] = xstar_of(p->noise_var[i], p->cutoff);
-      const double l = floor(2.0 * D.xstar[i] / p->grid.h[i]) + 1.0;
+      if (nz.kind == AMY_NOISE_NORMAL) D.xstar[i] = zh;
+      const double len = (zh - zl) / p->grid.h[i];
+      // cells kept: centres in an interval of length len h (at most
+      // floor(len) + 1), or cells meeting it (at most ceil(len) + 1)
+      const double l = (D.wrule == AMY_WINDOW_CENTRE) ? floor(len) + 1.0 : ceil(len) + 1.0;
       if (l < (double)L) L = (int)l;
-      D.win_a[i] = (D.xstar[i] + D.lo[i]) * D.inv_h[i] + 0.5;
-      D.win_b[i] = (D.lo[i] - D.xstar[i]) * D.inv_h[i] + 0.5;
-    } else {
-      D.xstar[i] = INFINITY;
+      const double half = (D.wrule == AMY_WINDOW_CENTRE) ? 0.5 : 0.0;
+      D.win_a[i] = (D.lo[i] - zl) * D.inv_h[i] + half;
+      D.win_b[i] = (D.lo[i] - zh) * D.inv_h[i] + half;
     }
     D.L[i] = L;
     W *= L;
@@ -354,6 +503,20 @@ void amy_make_plan(const amy_problem* p, Plan* pl) {
     nu *= p->inputs.count[k];
   }
   D.n_u = nu;
+  // disturbance digits follow the inputs in the walk
+  D.pd = p->dist.p;
+  D.nd = m + D.pd;
+  int nw = 1;
+  for (int l = 0; l < D.pd; ++l) {
+    const int k = m + l;
+    D.ucount[k] = p->dist.count[l];
+    D.ulo[k] = p->dist.lo[l];
+    D.uhi[k] = p->dist.hi[l];
+    D.ustep[k] = (p->dist.count[l] > 1) ? (p->dist.hi[l] - p->dist.lo[l]) / (double)(p->dist.count[l] - 1) : 0.0;
+    nw *= p->dist.count[l];
+  }
+  D.n_w = nw;
+  D.n_rows = nu * nw;
   for (int i = 0; i < AMY_MAX_DIM; ++i) {
     D.tlo[i] = p->target.lo[i];
     D.thi[i] = p->target.hi[i];
@@ -364,7 +527,7 @@ void amy_make_plan(const amy_problem* p, Plan* pl) {
   }
   for (int k = 0; k < p->dyn.n_params; ++k) D.params[k] = p->dyn.params[k];
   pl->W = W;
-  pl->rows = nx * (int64_t)nu;
+  pl->rows = nx * (int64_t)nu * nw;
   pl->f64 = (p->precision == AMY_FP64);
 }
 
@@ -385,7 +548,7 @@ void amy_layout(Plan* pl, int mode) {
   pl->stored_bytes = 0;
   if (mode == AMY_MODE_STORED) {
     const uint64_t tiles = (nx + 63) / 64;
-    const uint64_t rows_p = tiles * 64 * (uint64_t)D.n_u;
+    const uint64_t rows_p = tiles * 64 * (uint64_t)D.n_rows;
     pl->off_T = o;    o = align256(o + rows_p * (uint64_t)pl->W * vs);
     pl->off_org = o;  o = align256(o + rows_p * 4 + (uint64_t)pl->W * 4);  // + slot offsets
     pl->stored_bytes = o - pl->off_T;
@@ -420,6 +583,9 @@ static void plan_group(Plan* pl, int G) {
 amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   amy_make_plan(p, pl);
   int mode = p->mode == AMY_MODE_AUTO ? AMY_MODE_OTF : p->mode;
+  const bool user = p->dyn.kind == AMY_DYN_USER;
+  if (user && mode == AMY_MODE_STORED)
+    return amy_fail(AMY_E_UNSUPPORTED, "dynamics given as text run on the fly only");
   if (mode == AMY_MODE_STORED && (int64_t)pl->dev.W != pl->W)
     return amy_fail(AMY_E_UNSUPPORTED, "window of %lld slots too large to store", (long long)pl->W);
   amy_layout(pl, mode);
@@ -429,20 +595,33 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   // variants that fit: one lane per state needs every lane's 1-D tables in
   // LDS; the group variants need one set per state of the block
   const bool lanes_ok = (plan_tables(p, pl) == AMY_OK);
-  const bool fixed_ok = lanes_ok && amy_fixed_available(pl->dev);
+  // the compiled-shape sweeps build normal masses with the centre rule for
+  // rows without a disturbance; everything else runs the run-time-window ones
+  const bool plain = pl->dev.pd == 0 && pl->dev.noise == AMY_NOISE_NORMAL && pl->dev.wrule == AMY_WINDOW_CENTRE &&
+                     !pl->dev.mult;
+  const bool fixed_ok = lanes_ok && plain && amy_fixed_available(pl->dev);
   const bool fac_ok = fixed_ok && mode == AMY_MODE_OTF && amy_fac_available(pl->dev);
   int64_t sum_l = 0;
   for (int i = 0; i < pl->dev.n; ++i) sum_l += pl->dev.L[i];
   const int64_t msz = pl->f64 ? 8 : 4;
   const bool g16_ok = 4 * ((sum_l + 1) & ~1) * msz <= LDS_BUDGET;
   const bool g64_ok = ((sum_l + 1) & ~1) * msz <= LDS_BUDGET;
+  // one wave per state, lanes over inputs: normal noise, on the fly, built-in
+  // families, and uncached per-lane tables that fit
+  bool inputs_ok = mode == AMY_MODE_OTF && !user && pl->dev.noise == AMY_NOISE_NORMAL && !pl->dev.mult;
+  if (inputs_ok) {
+    Plan q = *pl;
+    inputs_ok = plan_tables(p, &q, true) == AMY_OK;
+  }
   auto feasible = [&](int v) {
+    if (user && (v == AMY_VARIANT_FIXED || v == AMY_VARIANT_FACTORED)) return false;
     switch (v) {
       case AMY_VARIANT_LANES: return lanes_ok;
       case AMY_VARIANT_FIXED: return fixed_ok;
       case AMY_VARIANT_FACTORED: return fac_ok;
       case AMY_VARIANT_GROUP16: return g16_ok && mode == AMY_MODE_OTF;
       case AMY_VARIANT_GROUP64: return g64_ok && mode == AMY_MODE_OTF;
+      case AMY_VARIANT_INPUTS: return inputs_ok;
     }
     return false;
   };
@@ -459,8 +638,11 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
     // one lane per state while its tables leave room for >= 6 waves per CU
     // and the window is small; otherwise lanes share a state's window
     const bool lanes_light = lanes_ok && pl->dev.lds_bytes_tail <= 24 * 1024 && pl->W < 1024;
+    // few states with many rows each: one wave per state keeps the GPU busy
+    const bool few_states = (pl->dev.n_x + 63) / 64 < 1024 && pl->dev.n_u >= 16;
     if (fac_ok) v = AMY_VARIANT_FACTORED;
     else if (fixed_ok) v = AMY_VARIANT_FIXED;
+    else if (inputs_ok && few_states) v = AMY_VARIANT_INPUTS;
     else if (lanes_light) v = AMY_VARIANT_LANES;
     else if (pl->W >= 4096 && g64_ok) v = AMY_VARIANT_GROUP64;
     else if (g16_ok) v = AMY_VARIANT_GROUP16;
@@ -470,6 +652,7 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
       return amy_fail(AMY_E_UNSUPPORTED, "window tables need %lld B of LDS even for one state per wave",
                       (long long)(sum_l * msz));
   }
+  if (v == AMY_VARIANT_INPUTS) plan_tables(p, pl, true);
   pl->dev.variant = v;
   pl->dev.rel_entries = 0;
   pl->dev.tables = 0;
@@ -509,6 +692,7 @@ static void fill_info(const amy_problem* p, const Plan& pl, amy_info* info) {
                            ? pl.dev.lds_bytes_fixed : pl.dev.lds_bytes);
   info->n_x = pl.dev.n_x;
   info->n_u = pl.dev.n_u;
+  info->n_w = pl.dev.n_w;
   info->rows = pl.rows;
   info->W = pl.W;
   info->workspace_bytes = pl.ws_bytes;
@@ -542,6 +726,7 @@ hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_
   const SweepKind sk = pl.f64 ? SWEEP_F64 : (last ? SWEEP_F32_LAST : SWEEP_F32);
   void* out = last ? (void*)V_out : Vb[cur ^ 1];
   int16_t* pk = pol ? pol + (int64_t)(k - 1) * D.n_x : nullptr;
+  if (pl.user) return amy_user_launch_sweep(pl.user, D, (int)sk, Vb[cur], out, label, pk, tail, st);
   if (pl.mode == AMY_MODE_STORED)
     return amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
                                    label, pk, st);
@@ -576,7 +761,9 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
     return amy_hip_fail(e, "init kernel");
   // the FP64 tail pass rides on the first kernel that builds every row
   // (the stored-mode build, else the first sweep); alone only when T_d = 0
-  if (want_tail && horizon == 0 && (e = amy_launch_tail(D, label, tailmax, st)) != hipSuccess)
+  if (want_tail && horizon == 0 &&
+      (e = pl.user ? amy_user_launch_tail(pl.user, D, label, tailmax, st) : amy_launch_tail(D, label, tailmax, st)) !=
+          hipSuccess)
     return amy_hip_fail(e, "tail kernel");
   const bool stored = (pl.mode == AMY_MODE_STORED);
   if ((e = amy_enqueue_prepare(pl, st, ws, horizon)) != hipSuccess) return amy_hip_fail(e, "table kernel");
@@ -603,13 +790,17 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
   return AMY_OK;
 }
 
-extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
-                                double* V_out, int16_t* policy_out, amy_info* info) {
+static amy_status solve_impl(const amy_problem* p, const amy_user_dynamics* user, void* stream, void* workspace,
+                             uint64_t ws_bytes, double* V_out, int16_t* policy_out, amy_info* info) {
   amy_status st = amy_validate(p);
   if (st != AMY_OK) return st;
+  if (user && (st = amy_user_check(user, p)) != AMY_OK) return st;
+  if (!user && p->dyn.kind == AMY_DYN_USER)
+    return amy_fail(AMY_E_INVALID, "dynamics given as text are solved with amy_solve_user");
   Plan pl;
   st = amy_resolve(p, ws_bytes, &pl);
   if (st != AMY_OK) return st;
+  pl.user = user;
   if (!workspace || !V_out) return amy_fail(AMY_E_INVALID, "workspace or V_out is NULL");
   if (((uintptr_t)workspace & 255) != 0) return amy_fail(AMY_E_INVALID, "workspace not 256-byte aligned");
   hipStream_t hs = (hipStream_t)stream;
@@ -652,4 +843,15 @@ extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* worksp
   if (tp)
     for (int i = 0; i < Timing::N; ++i) hipEventDestroy(tm.ev[i]);
   return st;
+}
+
+extern "C" amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
+                                double* V_out, int16_t* policy_out, amy_info* info) {
+  return solve_impl(p, nullptr, stream, workspace, ws_bytes, V_out, policy_out, info);
+}
+
+extern "C" amy_status amy_solve_user(const amy_user_dynamics* f, const amy_problem* p, void* stream, void* workspace,
+                                     uint64_t ws_bytes, double* V_out, int16_t* policy_out, amy_info* info) {
+  if (!f) return amy_fail(AMY_E_INVALID, "user dynamics handle is NULL");
+  return solve_impl(p, f, stream, workspace, ws_bytes, V_out, policy_out, info);
 }

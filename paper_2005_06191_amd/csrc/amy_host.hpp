@@ -6,8 +6,11 @@
 #include "../../include/amytiss.h"
 #include "amy_plan.hpp"
 
+struct amy_user_dynamics;
+
 struct Plan {
   DevProblem dev;
+  const amy_user_dynamics* user = nullptr;  // AMY_DYN_USER: the compiled right-hand side
   int64_t W;        // slots per row (may exceed INT32 for huge windows)
   int64_t rows;     // n_x * n_u
   bool f64;         // FP64 path
@@ -25,6 +28,13 @@ struct Timing {
 };
 
 amy_status amy_fail(amy_status st, const char* fmt, ...);
+// run-time-compiled dynamics (amy_rtc.cpp)
+amy_status amy_user_check(const amy_user_dynamics* f, const amy_problem* p);
+hipError_t amy_user_launch_sweep(const amy_user_dynamics* f, const DevProblem& P, int sk, const void* Vin,
+                                 void* Vout, const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
+                                 hipStream_t st);
+hipError_t amy_user_launch_tail(const amy_user_dynamics* f, const DevProblem& P, const uint8_t* label,
+                                unsigned long long* tailmax, hipStream_t st);
 amy_status amy_hip_fail(hipError_t e, const char* what);
 amy_status amy_validate(const amy_problem* p);
 void amy_make_plan(const amy_problem* p, Plan* pl);
@@ -64,6 +74,8 @@ struct BatchTune {
 };
 
 amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp);
+// Workgroups of `lds` bytes of LDS resident on one CU of device dev.
+int amy_lds_blocks_per_cu(int dev, size_t lds);
 amy_status amy_batch_normalise(const amy_problem* p, Plan* pl);
 amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStream_t hs, char* ws,
                          double* const* V_out, int16_t* const* policy_out, bool want_tail, const BatchTune& tune,

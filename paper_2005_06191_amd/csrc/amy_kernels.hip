@@ -14,6 +14,7 @@ DECL_FAMILY(affine)
 DECL_FAMILY(room)
 DECL_FAMILY(unicycle)
 DECL_FAMILY(vehicle7)
+DECL_FAMILY(robot)
 
 #define AMY_DISPATCH(OP, ...)                                                \
   switch (P.kind) {                                                           \
@@ -21,6 +22,7 @@ DECL_FAMILY(vehicle7)
     case AMY_DYN_ROOM_: return amy_gen_room_##OP(__VA_ARGS__);               \
     case AMY_DYN_UNICYCLE_: return amy_gen_unicycle_##OP(__VA_ARGS__);       \
     case AMY_DYN_VEHICLE7_: return amy_gen_vehicle7_##OP(__VA_ARGS__);       \
+    case AMY_DYN_ROBOT_: return amy_gen_robot_##OP(__VA_ARGS__);             \
   }                                                                           \
   return hipErrorInvalidValue;
 

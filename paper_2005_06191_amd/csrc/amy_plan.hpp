@@ -5,7 +5,9 @@
 // kernel argument (< 4 KB), so every field is uniform across a launch and
 // lives in scalar registers.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <stdint.h>
+#endif
 
 #define AMY_MAXD 8
 #define AMY_MAXI 4
@@ -23,6 +25,21 @@ enum { LBL_FREE = 0, LBL_ZERO = 1, LBL_ONE = 2 };
 
 struct DevProblem {
   int32_t n, m, kind, spec;
+  // Disturbance (Def. 3.1): the input walk runs over nd = m + pd digits,
+  // the m inputs then the pd disturbance dimensions (their counts, lower
+  // ends and steps in ucount / ulo / ustep from index m on); every state has
+  // n_rows = n_u n_w rows (x, u, w), disturbance fastest.
+  int32_t pd, nd, n_w, n_rows;
+  // Noise model: 0 normal (sigma from the variance), 1 uniform on [a, b],
+  // 2 exponential with rate lambda, 3 beta(alpha, beta) on [a, b].  The
+  // standardised edge coordinate is z = (edge - mu) inv_sigma with
+  // inv_sigma = 1/sigma, 1/(b - a), lambda, 1/(b - a); zoff = a/(b - a)
+  // for the supports that start at a (the support is z - zoff in [0, 1]).
+  // wrule: 0 keeps the cells whose centre lies in the cutting interval,
+  // 1 the cells that intersect it.  mult: normal noise scaled by the
+  // state's own coordinate (Eq. 3.2, multiplicative), no cut.
+  int32_t noise, wrule, mult, pad0;
+  double zoff[AMY_MAXD], balpha[AMY_MAXD], bbeta[AMY_MAXD];
   int32_t count[AMY_MAXD];
   int32_t L[AMY_MAXD];        // fixed window length per dimension
   int32_t ucount[AMY_MAXI];
@@ -77,9 +94,12 @@ struct DevProblem {
   int64_t stride[AMY_MAXD];   // state index strides, last dimension fastest
   double lo[AMY_MAXD], h[AMY_MAXD], inv_h[AMY_MAXD];
   double inv_sigma[AMY_MAXD], xstar[AMY_MAXD];
-  // window rule precomputed per dimension: kept cells are
-  // ceil(mu inv_h - win_a) .. floor(mu inv_h - win_b), with
-  // win_a = (x* + lo) inv_h + 1/2 and win_b = (lo - x*) inv_h + 1/2;
+  // window rule precomputed per dimension for the cutting interval
+  // [mu + zl, mu + zh] (normal: zl = -x*, zh = x*): the centre rule keeps
+  // ceil(mu inv_h - win_a) .. floor(mu inv_h - win_b) with
+  // win_a = (lo - zl) inv_h + 1/2 and win_b = (lo - zh) inv_h + 1/2; the
+  // intersect rule keeps floor(mu inv_h - win_a) .. ceil(mu inv_h - win_b) - 1
+  // with win_a = (lo - zl) inv_h and win_b = (lo - zh) inv_h;
   // edge j sits at z = (lo - mu) inv_sigma + j hs, hs = h inv_sigma.
   double win_a[AMY_MAXD], win_b[AMY_MAXD], hs[AMY_MAXD];
   double ulo[AMY_MAXI], ustep[AMY_MAXI], uhi[AMY_MAXI];

@@ -427,6 +427,8 @@ extern "C" amy_status amy_server_submit(amy_server* s, const amy_problem* p, int
   if (!s || !p || !ticket) return amy_fail(AMY_E_INVALID, "NULL argument");
   amy_status st = amy_validate(p);
   if (st != AMY_OK) return st;
+  if (p->dyn.kind == AMY_DYN_USER)
+    return amy_fail(AMY_E_UNSUPPORTED, "the server takes the built-in dynamics families");
   Request* r = new Request();
   r->prob = *p;
   r->want_policy = want_policy != 0;
@@ -460,7 +462,10 @@ extern "C" amy_status amy_server_submit(amy_server* s, const amy_problem* p, int
   // large requests, and families the batched kernel lacks, take their own
   // launch per step; the rest share the batched step, which runs the
   // run-time-window code (same bits as the compiled-shape sweep)
-  r->solo = r->plan.dev.n_x >= SOLO_STATES || !amy_batch_supports(r->plan.dev.kind, r->plan.dev.n, r->plan.mode);
+  // (so do requests with a disturbance or another noise model)
+  const DevProblem& Dp = r->plan.dev;
+  const bool plain = Dp.pd == 0 && Dp.noise == 0 && Dp.wrule == 0 && !Dp.mult;
+  r->solo = Dp.n_x >= SOLO_STATES || !plain || !amy_batch_supports(Dp.kind, Dp.n, r->plan.mode);
   if (!r->solo) {
     q.mode = r->plan.mode;
     st = amy_batch_normalise(&q, &r->plan);

@@ -106,7 +106,7 @@ extern "C" amy_status amy_tune_solve(const amy_problem* p, void* stream, void* w
   if (st != AMY_OK) return st;
   std::vector<int> variants;
   for (int v : {AMY_VARIANT_LANES, AMY_VARIANT_FIXED, AMY_VARIANT_GROUP16, AMY_VARIANT_GROUP64,
-                AMY_VARIANT_FACTORED}) {
+                AMY_VARIANT_FACTORED, AMY_VARIANT_INPUTS}) {
     amy_problem q = *p;
     q.variant = v;
     Plan pl;
@@ -170,14 +170,23 @@ extern "C" amy_status amy_tune_batch(const amy_problem* probs, int32_t count, vo
   Entry best;
   best.ms = 1e300;
   double worst = 0.0;
+  int valid = 0;
   for (const BatchTune& t : cands) {
     double ms = 1e300;
+    bool gave_up = false;
     for (int rep = 0; rep < 2; ++rep) {
       float m = 0.f;
       st = amy_batch_run(probs, bp, hs, (char*)workspace, V_out, nullptr, false, t, &m);
       if (st != AMY_OK) return st;
+      // a candidate whose grid-barrier wait gave up produced no valid result
+      unsigned ctl[4] = {0u, 0u, 0u, 0u};
+      const hipError_t e = hipMemcpy(ctl, (char*)workspace + bp.off_ctl, sizeof ctl, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return amy_hip_fail(e, "batch control readback");
+      if (ctl[2] != 0u) gave_up = true;
       if (rep > 0) ms = std::min(ms, (double)m);
     }
+    if (gave_up) continue;
+    ++valid;
     worst = std::max(worst, ms);
     if (ms < best.ms) {
       best.ms = ms;
@@ -186,8 +195,9 @@ extern "C" amy_status amy_tune_batch(const amy_problem* probs, int32_t count, vo
       best.blocks_per_cu = t.blocks_per_cu;
     }
   }
+  if (valid == 0) return amy_fail(AMY_E_DEVICE, "batch tuning: every candidate's grid barrier gave up");
   store(key_batch(probs, count, bp), best);
-  fill_result(out, best, (int)cands.size(), worst);
+  fill_result(out, best, valid, worst);
   return AMY_OK;
 }
 
@@ -246,7 +256,7 @@ extern "C" amy_status amy_tune_load(const char* path) {
     if (sscanf(body.c_str(), "{\"chunk\": %d, \"blocks_per_cu\": %d, \"xcd_order\": %d, \"variant\": %d, \"ms\": %lf}",
                &e.chunk, &e.blocks_per_cu, &e.xcd_order, &e.variant, &e.ms) != 5)
       return amy_fail(AMY_E_INVALID, "%s: malformed entry for %s", path, key.c_str());
-    if (e.chunk < 1 || e.chunk > 64 || e.blocks_per_cu < 0 || e.variant < 0 || e.variant > AMY_VARIANT_FACTORED)
+    if (e.chunk < 1 || e.chunk > 64 || e.blocks_per_cu < 0 || e.variant < 0 || e.variant > AMY_VARIANT_INPUTS)
       return amy_fail(AMY_E_INVALID, "%s: out-of-range entry for %s", path, key.c_str());
     loaded[key] = e;
     pos = b1 + 1;

@@ -112,3 +112,34 @@ def test_variant_choice_on_the_host(A):
         with pytest.raises(A.AmyError) as e:
             A.query(p, variant="factored")
         assert e.value.status == A.binding.E_UNSUPPORTED
+
+
+def test_grid_from_quantization_matches_printed_pair_counts(A):
+    """The C helper of the paper's quantisation convention reproduces the
+    pair counts |X x U| printed in Sec. 7 and Table 4."""
+    import json
+    import numpy as np
+    with open(os.path.join(ROOT, "tests", "golden", "paper_sizes.json")) as fh:
+        cases = json.load(fh)["cases"]
+    for c in cases:
+        lo, h, cx = A.grid_from_quantization(c["x_lb"], c["x_ub"], c["x_q"])
+        ulo, uhi, cu = A.inputs_from_quantization(c["u_lb"], c["u_ub"], c["u_q"])
+        assert int(np.prod(cx)) * int(np.prod(cu)) == c["pairs"], c["name"]
+        for i in range(len(cx)):
+            assert lo[i] == c["x_lb"][i] - c["x_q"][i] / 2 and h[i] == c["x_q"][i]
+        for k in range(len(cu)):
+            assert ulo[k] == c["u_lb"][k]
+            assert abs(uhi[k] - c["u_ub"][k]) <= 1e-9 * max(1.0, abs(c["u_ub"][k]))
+        # the Python description helper agrees
+        assert W.grid_from_quantization(c["x_lb"], c["x_ub"], c["x_q"])[2] == cx
+
+
+def test_grid_from_quantization_errors(A):
+    with pytest.raises(A.AmyError):
+        A.grid_from_quantization([0.0], [1.0], [0.0])
+    with pytest.raises(A.AmyError):
+        A.grid_from_quantization([1.0], [0.0], [0.1])
+    with pytest.raises(A.AmyError):
+        A.inputs_from_quantization([0.0] * 5, [1.0] * 5, [0.5] * 5)
+    with pytest.raises(A.AmyError):
+        A.grid_from_quantization([0.0], [math.inf], [0.1])

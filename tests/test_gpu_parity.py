@@ -304,3 +304,63 @@ def test_vehicle7_full_fixed_vs_generic_first_step():
     a = A.solve(p, variant="fixed", policy=False)
     b = A.solve(p, variant="lanes", policy=False)
     assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())
+
+
+# ------------------------------------- full sizes against the oracle itself
+
+@pytest.fixture(scope="module")
+def uni_oracle(orc):
+    """The oracle's whole-horizon solve of the unicycle workload at full size
+    (600,000 states x 45 inputs x 16 steps; about a minute on 16 threads)."""
+    p = W.unicycle3d(precision="fp64")
+    say(f"[oracle] full unicycle solve: {p.rows * p.horizon:.3g} row-updates ...")
+    return p, orc.solve(p, gap=True)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,mode", [("fp32", "otf"), ("fp64", "otf"), ("fp32", "stored")])
+def test_full_size_unicycle_whole_horizon_vs_oracle(uni_oracle, prec, mode):
+    """Every state of the 100 x 100 x 60 unicycle workload after all 16 steps,
+    in the bench's launch configuration (FP32 and FP64 on the fly, FP32 with
+    the 5.4 GB of stored rows), against the oracle's own full solve."""
+    p0, ref = uni_oracle
+    p = p0.with_(precision=prec, mode=mode)
+    tol = TOL_FP64 if prec == "fp64" else TOL_FP32
+    say(f"[full-oracle] unicycle {prec} {mode}")
+    V, pol, info = gpu_solve(p)
+    err = compare(p, ref, V, pol, tol, gap=ref["gap"])
+    assert abs(info["max_row_tail"] - ref["max_tail"]) <= 1e-13 + 1e-9 * ref["max_tail"]
+    say(f"[full-oracle] unicycle {prec} {mode} ({info['variant']}): max |V - V_oracle| = {err:.2e}")
+
+
+def _chained(orc, p, n_states=1000, seed=3):
+    """The last Bellman step at full size against the oracle: the plain FP64
+    GPU path solves the problem with one step fewer (its V at k = 1 is V_2 of
+    the full horizon); the oracle takes step k = 1 from that vector at
+    sampled states, each on its own, and the GPU's full-horizon V_1 and
+    policy of step 1 (FP32 and FP64) are compared with it.  The FP32 solve
+    runs every step in FP32, so its error includes that of all T_d steps."""
+    Vn, _, _ = gpu_solve(p.with_(precision="fp64", horizon=p.horizon - 1), policy=False)
+    rng = np.random.default_rng(seed)
+    states = np.unique(np.concatenate([rng.integers(0, p.n_x, n_states), [0, p.n_x - 1]]))
+    Vr, pr, gap = orc.step(p.with_(precision="fp64"), states, V_next=Vn)
+    out = {}
+    for prec, tol in (("fp32", TOL_FP32), ("fp64", TOL_FP64)):
+        V, pol, info = gpu_solve(p.with_(precision=prec))
+        err = float(np.abs(V[states] - Vr).max())
+        assert err <= tol, f"{p.name} {prec}: {err:.3e} > {tol:.1e}"
+        clear = gap > 2 * tol
+        bad = int((pol[0][states][clear] != pr[clear]).sum())
+        assert bad == 0, f"{p.name} {prec}: {bad} policy entries differ"
+        out[prec] = (err, info["variant"])
+    return out, len(states)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["room5-20^5", "vehicle7-8^7", "unicycle-100x100x60"])
+def test_full_size_last_step_chained_vs_oracle(orc, name):
+    p = FULL[name]()
+    say(f"[chained] {name}: n_x={p.n_x} n_u={p.n_u} T_d={p.horizon}")
+    out, n = _chained(orc, p)
+    say(f"[chained] {name}: over {n} states max err fp32 {out['fp32'][0]:.2e} ({out['fp32'][1]}), "
+        f"fp64 {out['fp64'][0]:.2e} ({out['fp64'][1]})")

@@ -33,7 +33,7 @@ import numpy as np
 
 INF = float("inf")
 
-DYN_KINDS = ("affine", "unicycle", "room", "vehicle7", "robot")
+DYN_KINDS = ("affine", "unicycle", "room", "vehicle7", "robot", "user")
 SPECS = ("safety", "reach", "reach_avoid")
 MODES = ("auto", "stored", "otf")
 PRECISIONS = ("fp64", "fp32")
@@ -83,6 +83,11 @@ class Problem:
     noise_b: Tuple[float, ...] = ()
     noise_alpha: Tuple[float, ...] = ()
     noise_beta: Tuple[float, ...] = ()
+    # sweep variant the GPU library is asked for ("auto" lets it choose)
+    variant: str = "auto"
+    # dyn == "user": the right-hand side as source text, the body of
+    # rhs(x, u, w, params, mu) (Sec. 3: f given as text)
+    rhs: str = ""
 
     @property
     def n(self) -> int:
@@ -368,3 +373,73 @@ def serving_stream(count: int = 500, seed: int = 20265, qps: float = 10.0,
             p = scaled_family(parent, _loguniform(rng, nx_lo, nx_hi))
         out.append((t, p.with_(name=f"req{r}-{p.name}")))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Road traffic (Sec. 8.3.1) and the robot (Sec. 7), also as source text.
+# ---------------------------------------------------------------------------
+
+# Sec. 8.3.1: cells of 0.5 km, flow speed 100 km/h, sampling time 6.48 s,
+# so a cell passes tau v / L = 0.36 of its vehicles on; a quarter of what
+# leaves cells 1 and 3 takes the exit (q = 0.25); the lights admit 6 and 8
+# vehicles.  Cell i receives from cell i - 1 (cell 1 from cell 5).
+TRAFFIC_FLOW, TRAFFIC_EXIT = 0.36, 0.25
+
+TRAFFIC5_RHS = """
+const double a = params[0], q = params[1];
+mu[0] = ((1.0 - a) * x[0] + a * x[4]) + 6.0 * u[0];
+mu[1] = (1.0 - a - q) * x[1] + a * x[0];
+mu[2] = ((1.0 - a) * x[2] + a * x[1]) + 8.0 * u[1];
+mu[3] = (1.0 - a - q) * x[3] + a * x[2];
+mu[4] = (1.0 - a) * x[4] + a * x[3];
+"""
+
+ROBOT_RHS = """
+const double a = params[0] * u[0];
+mu[0] = (x[0] + a * cos(u[1])) + w[0];
+mu[1] = (x[1] + a * sin(u[1])) + w[0];
+"""
+
+
+def traffic5d(q: float = 0.37, precision: str = "fp32", horizon: int = 7, text: bool = False,
+              var: float = 0.7, cutoff: float = 2e-2, lo=(0.0,) * 5, hi=(10.0,) * 5) -> Problem:
+    """The 5-cell road traffic ring of Sec. 8.3.1: X = [0, 10]^5 quantised by
+    0.37 (28 points per cell), the two lights in {0, 1}, noise covariance
+    diag(0.7, ...), cutoff 2e-2, safety (density below 10 in every cell),
+    horizon 7.  text=True gives the same model as source text (dyn "user")."""
+    a, e = TRAFFIC_FLOW, TRAFFIC_EXIT
+    A = np.zeros((5, 5))
+    for i in range(5):
+        A[i, i] = 1.0 - a - (e if i in (1, 3) else 0.0)
+        A[i, (i - 1) % 5] = a
+    B = np.zeros((5, 2))
+    B[0, 0], B[2, 1] = 6.0, 8.0
+    lo_, h, cnt = grid_from_quantization(lo, hi, (q,) * 5)
+    p = Problem(lo=lo_, h=h, count=cnt, u_lo=(0.0, 0.0), u_hi=(1.0, 1.0), u_count=(2, 2), dyn="affine",
+                params=affine_params(A, B), var=(var,) * 5, cutoff=cutoff, horizon=horizon, spec="safety",
+                safe=box((0.0,) * 5, (10.0,) * 5, 5), mode="otf", precision=precision,
+                name="traffic5d" + ("-text" if text else ""))
+    if text:
+        p = p.with_(dyn="user", params=(a, e), rhs=TRAFFIC5_RHS)
+    return p
+
+
+def robot2d(input_q: float = 0.2, precision: str = "fp32", horizon: int = 8, spec: str = "safety",
+            text: bool = False) -> Problem:
+    """The robot of Sec. 7 with its disturbance: X = [-10, 10]^2 quantised by
+    0.5, U = [-1, 1]^2 quantised by ``input_q`` (0.2 gives the 203,401
+    state-input pairs printed there), W = [-1, 1] quantised by 0.2,
+    covariance diag(0.75, 0.75), cutoff 1e-3, tau = 10, safety over 8 steps
+    (or reach-avoid with the seeded boxes below).  text=True gives the same
+    model as source text."""
+    lo, h, cnt = grid_from_quantization((-10, -10), (10, 10), (0.5, 0.5))
+    ulo, uhi, ucnt = inputs_from_quantization((-1, -1), (1, 1), (input_q, input_q))
+    wlo, whi, wcnt = inputs_from_quantization((-1,), (1,), (0.2,))
+    p = Problem(lo=lo, h=h, count=cnt, u_lo=ulo, u_hi=uhi, u_count=ucnt, dyn="robot", params=(10.0,),
+                var=(0.75, 0.75), cutoff=1e-3, horizon=horizon, spec=spec, w_lo=wlo, w_hi=whi, w_count=wcnt,
+                mode="otf", precision=precision, name="robot2d" + ("-text" if text else ""))
+    if spec == "reach_avoid":
+        p = p.with_(target=box((5.0, 5.0), (10.0, 10.0), 2), avoid=box((-2.0, -2.0), (2.0, 2.0), 2))
+    if text:
+        p = p.with_(dyn="user", rhs=ROBOT_RHS)
+    return p

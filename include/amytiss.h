@@ -299,6 +299,22 @@ amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_info* out);
 amy_status amy_solve(const amy_problem* p, void* stream, void* workspace, uint64_t ws_bytes,
                      double* V_out, int16_t* policy_out, amy_info* info);
 
+/* ------------------------------------------------- allocation-free solve
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid allocation): amy_solve
+ * without a workspace argument.  The library keeps one static workspace of
+ * AMY_STATIC_WORKSPACE_BYTES in the memory of every device it runs on (held
+ * until the process ends) and runs amy_solve's kernels on it.  The call
+ * only enqueues work on `stream`, like amy_solve with info == NULL, and
+ * allocates nothing.  V_out, policy_out: as for amy_solve (device buffers,
+ * caller-owned).  AMY_E_NOMEM when the problem's workspace (amy_query's
+ * workspace_bytes) exceeds the limit; other errors as amy_solve.  All calls
+ * on one device share that workspace: calls ordered on one stream are safe,
+ * calls whose work can overlap on one device (other streams, other threads)
+ * race and give undefined results. */
+#define AMY_STATIC_WORKSPACE_BYTES (96ull << 20)
+amy_status amy_solve_static(const amy_problem* p, void* stream, double* V_out, int16_t* policy_out);
+
 /* ------------------------------------------------- dynamics as source text
  * Sec. 3: the user gives the right-hand side of the difference equation as
  * text.  rhs is the body of a device function

@@ -163,6 +163,8 @@ def lib():
         for fn in ("amy_server_create", "amy_server_submit", "amy_server_wait", "amy_server_poll",
                    "amy_server_get_stats", "amy_server_reset_stats", "amy_server_destroy"):
             getattr(L, fn).restype = C.c_int
+        L.amy_solve_static.argtypes = [pp, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.amy_solve_static.restype = C.c_int
         dp = C.POINTER(C.c_double)
         L.amy_grid_from_quantization.argtypes = [C.c_int32, dp, dp, dp, C.POINTER(Grid)]
         L.amy_grid_from_quantization.restype = C.c_int
@@ -291,6 +293,25 @@ class Solver:
 def solve(p, policy: bool = True, info: bool = True, budget: int = 0, **kw) -> Result:
     """One solve; keyword overrides: mode=, precision=, variant=."""
     return Solver(p, budget=budget, **kw).solve(policy=policy, info=info)
+
+
+STATIC_WORKSPACE_BYTES = 96 << 20   # AMY_STATIC_WORKSPACE_BYTES
+
+
+def solve_static(p, policy: bool = True, stream=None, out=None, **kw) -> Result:
+    """amy_solve_static: the solve on the library's own static workspace (no
+    device allocation inside the call; V and the policy are allocated here,
+    by the caller's side, unless `out` is given).  Only enqueues the work."""
+    import torch
+    s = to_struct(p, **kw)
+    dev = torch.device("cuda")
+    n_x, T = p.n_x, p.horizon
+    V = out if out is not None else torch.empty(n_x, dtype=torch.float64, device=dev)
+    pol = torch.empty((T, n_x), dtype=torch.int16, device=dev) if (policy and T > 0) else None
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    check(lib().amy_solve_static(C.byref(s), C.c_void_p(st.cuda_stream), C.c_void_p(V.data_ptr()),
+                                 C.c_void_p(pol.data_ptr()) if pol is not None else None))
+    return Result(V, pol, None)
 
 
 def _quant_args(lb, ub, q):

@@ -253,6 +253,19 @@ def bench_batch(args):
     variants = {}
     for r in res:
         variants[r.info["variant"]] = variants.get(r.info["variant"], 0) + 1
+    # the alternative: the same systems solved one after another on one
+    # stream, each with its own AUTO variant and its workspace allocated once
+    solvers = [A.Solver(p) for p in ps]
+    for _ in range(args.warmup):
+        for sv in solvers:
+            sv.solve(policy=False, info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        for sv in solvers:
+            sv.solve(policy=False, info=False)
+    torch.cuda.synchronize()
+    seq_ms = 1e3 * (time.perf_counter() - t1) / args.steps
     out = {
         "metric": "Bellman (state,input) row-updates/sec FP32 vs FP64 at <=1e-5 err; p50/p99",
         "value": work * args.steps / wall, "unit": "row-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -261,6 +274,8 @@ def bench_batch(args):
         "config": {"workload": f"batch of {len(ps)} systems (2-D linear / 3-D unicycle), one persistent launch",
                    "systems": len(ps), "row_updates": work, "variants": variants, "tuned": tuned},
         "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
+        "sequential_ms_per_pass": round(seq_ms, 3),
+        "batch_speedup_vs_sequential": round(seq_ms / (1e3 * wall / args.steps), 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
                      "kernel": "k_batch_persistent (FP32)", "kernel_avg_ms": round(kms, 4)},

@@ -61,7 +61,8 @@ typedef enum {
   AMY_E_DEVICE = 3,      /* a HIP runtime call failed                        */
   AMY_E_UNSUPPORTED = 4, /* valid but not supported by this build            */
   AMY_E_BUSY = 5,        /* server queue full                                */
-  AMY_E_NOTREADY = 6     /* server: result not ready yet                     */
+  AMY_E_NOTREADY = 6,    /* server: result not ready yet                     */
+  AMY_E_CANCELLED = 7    /* server: the request was cancelled                */
 } amy_status;
 
 typedef enum { AMY_SAFETY = 0, AMY_REACH = 1, AMY_REACH_AVOID = 2 } amy_spec;
@@ -429,6 +430,7 @@ typedef struct {
   double row_updates;            /* completed requests' n_x n_u T_d          */
   double busy_s;                 /* worker time with work on the device      */
   double p50_ms, p99_ms, mean_ms;/* submit-to-result latency, completed      */
+  uint64_t cancelled;            /* requests cancelled before finishing      */
 } amy_server_stats;
 
 /* Serving form of Alg. 4 with the memory trade-off of Sec. 6.1 (stored rows
@@ -451,6 +453,13 @@ amy_status amy_server_poll(amy_server* s, uint64_t ticket, double* V_host, int16
                            amy_info* info);
 amy_status amy_server_wait(amy_server* s, uint64_t ticket, int32_t timeout_ms, double* V_host,
                            int16_t* policy_host, amy_info* info);
+/* Cancel a queued or running request.  A queued request leaves the queue at
+ * once; a running one leaves at the next step boundary (its steps already
+ * launched complete first), and its slot and arena space are freed then.
+ * poll / wait on the ticket then answer AMY_E_CANCELLED (and release it).
+ * AMY_E_INVALID for an unknown ticket or a request that has already finished
+ * (its result stays available). */
+amy_status amy_server_cancel(amy_server* s, uint64_t ticket);
 amy_status amy_server_get_stats(amy_server* s, amy_server_stats* out);
 amy_status amy_server_reset_stats(amy_server* s);
 /* Finishes the admitted requests, drops the queued ones, frees everything. */

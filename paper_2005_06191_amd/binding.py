@@ -17,8 +17,9 @@ LIB_PATH = os.environ.get("AMYTISS_LIB") or os.path.join(HERE, "libamytiss_hip.s
 
 MAX_DIM, MAX_IN, MAX_PARAMS = 8, 4, 128
 
-OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_NOTREADY = range(7)
-STATUS = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "BUSY", 6: "NOTREADY"}
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_BUSY, E_NOTREADY, E_CANCELLED = range(8)
+STATUS = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "UNSUPPORTED", 5: "BUSY", 6: "NOTREADY",
+          7: "CANCELLED"}
 DYN = {"affine": 0, "unicycle": 1, "room": 2, "vehicle7": 3, "robot": 4, "user": 5}
 NOISE = {"normal": 0, "uniform": 1, "exponential": 2, "beta": 3}
 WINDOW = {"centre": 0, "intersect": 1}
@@ -108,7 +109,7 @@ class ServerStats(C.Structure):
                 ("queued", C.c_int32), ("active", C.c_int32), ("max_active", C.c_int32),
                 ("hbm_in_use", C.c_uint64), ("hbm_peak", C.c_uint64), ("steps", C.c_uint64),
                 ("row_updates", C.c_double), ("busy_s", C.c_double), ("p50_ms", C.c_double),
-                ("p99_ms", C.c_double), ("mean_ms", C.c_double)]
+                ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("cancelled", C.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -160,8 +161,9 @@ def lib():
         L.amy_server_get_stats.argtypes = [sp, C.POINTER(ServerStats)]
         L.amy_server_reset_stats.argtypes = [sp]
         L.amy_server_destroy.argtypes = [sp]
+        L.amy_server_cancel.argtypes = [sp, C.c_uint64]
         for fn in ("amy_server_create", "amy_server_submit", "amy_server_wait", "amy_server_poll",
-                   "amy_server_get_stats", "amy_server_reset_stats", "amy_server_destroy"):
+                   "amy_server_get_stats", "amy_server_reset_stats", "amy_server_destroy", "amy_server_cancel"):
             getattr(L, fn).restype = C.c_int
         L.amy_solve_static.argtypes = [pp, C.c_void_p, C.c_void_p, C.c_void_p]
         L.amy_solve_static.restype = C.c_int
@@ -499,6 +501,11 @@ class Server:
 
     def wait(self, ticket: int, timeout_ms: int = -1):
         return self._collect(lib().amy_server_wait, ticket, C.c_int32(int(timeout_ms)))
+
+    def cancel(self, ticket: int):
+        """Cancel a queued or running request; its poll / wait then raise
+        AmyError with status E_CANCELLED."""
+        check(lib().amy_server_cancel(self._h, C.c_uint64(int(ticket))))
 
     def stats(self) -> dict:
         st = ServerStats()

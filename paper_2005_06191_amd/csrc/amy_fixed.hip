@@ -193,6 +193,16 @@ __device__ __forceinline__ void contract_step(const DevProblem& P, const FixedRo
   accum_step<D, SH, MT, AT, COMP, LL>(R, k, inner, acc, c, ll);
 }
 
+// The value of v, hidden from the optimiser: the select chain below then
+// stays a chain of selects instead of being folded back into an indexed
+// access of the row's mass array, which would put that array in scratch
+// memory (an empty asm statement: no instruction is emitted).
+template <class T>
+__device__ __forceinline__ T opaque_value(T v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 // acc += mass of slot k of level D times inner (compensated at level 0).
 template <int D, class SH, class MT, class AT, bool COMP, int LL>
 __device__ __forceinline__ void accum_step(const FixedRow<SH, MT>& R, int k, AT inner, AT& acc, AT& c,
@@ -204,9 +214,9 @@ __device__ __forceinline__ void accum_step(const FixedRow<SH, MT>& R, int k, AT 
     if constexpr (LL > 0) {
       mk = ll[(D * SH::LMAX + k) * LL];
     } else {
-      mk = R.m[D][0];
+      mk = opaque_value(R.m[D][0]);
 #pragma unroll
-      for (int j = 1; j < SH::L[D]; ++j) mk = (k == j) ? R.m[D][j] : mk;
+      for (int j = 1; j < SH::L[D]; ++j) mk = (k == j) ? opaque_value(R.m[D][j]) : mk;
     }
   } else {
     mk = R.m[D][k];
@@ -837,7 +847,9 @@ __device__ __forceinline__ int origin_of(MT v) {
 // Entry e is the record rm[e*REC .. e*REC+REC): the masses of its window, zeros,
 // and the window origin's bits in the last slot; wg[2e], wg[2e+1]: its FP64
 // kept-window and grid masses (the per-row tail's factors).
-template <int KIND, int N, class MT, int REC>
+// GEN: the masses of the other noise models (one entry's tables cost a few
+// hundred FP64 operations there, so memoising them matters most).
+template <int KIND, int N, class MT, int REC, bool GEN>
 __global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict__ rm, double* __restrict__ wg) {
   const int e = blockIdx.x * 64 + threadIdx.x;
   if (e >= P.rel_entries) return;
@@ -875,14 +887,15 @@ __global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict_
   for (int dd = 1; dd < N; ++dd)
     if (dd == i) m_i = mu[dd];
   MT t[REC];
-  const Win w = dim_table<MT>(P, i, m_i, t, 1);
+  const Win w = GEN ? dim_table_gen<MT>(P, i, m_i, t, 1, 1.0) : dim_table<MT>(P, i, m_i, t, 1);
   for (int k = P.L[i]; k < REC - 1; ++k) t[k] = MT(0);
   t[REC - 1] = origin_bits<MT>(w.o);
   MT* dst = rm + (int64_t)e * REC;
 #pragma unroll
   for (int k = 0; k < REC; ++k) dst[k] = t[k];
   double wm, gm;
-  win_grid_mass(P, i, w, wm, gm);
+  if constexpr (GEN) win_grid_mass_gen(P, i, w, wm, gm, m_i, 1.0);
+  else win_grid_mass(P, i, w, wm, gm);
   wg[2 * (int64_t)e] = wm;
   wg[2 * (int64_t)e + 1] = gm;
 }
@@ -1028,15 +1041,29 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI
 // whose window does not fit in it gathers from V as the other sweeps do.
 // The contraction is the same code with the same order of operations, so
 // the result is bitwise that of k_sweep_memo.
+//
+// The box is padded in LDS so that one read instruction of a wave hits
+// distinct banks.  A wave's 64 lanes are 4 x 4 x 4 states of dimensions
+// 2..4, and each LDS cycle serves 32 lanes (a 4 x 4 x 2 block) from 32
+// four-byte banks.  Their window origins step by about one cell per lane in
+// each of those dimensions, so rows of dimension 4 padded to 8 cells put the
+// 4 x 4 block on 16 distinct banks, and a dimension-2 stride of 20 mod 32
+// moves the other half of the block onto the remaining ones.  Dense strides
+// (6, 36) put pairs of lanes on one bank: the profiler counted 39% of the
+// LDS cycles stalled on bank conflicts.
 template <class SH>
 struct StageBox {
   static_assert(SH::N == 5, "staged box: 5-D shapes");
   static constexpr int C[5] = {SH::L[0] + 1, SH::L[1] + 3, SH::L[2] + 3, SH::L[3] + 3, SH::L[4] + 3};
-  static constexpr int S[5] = {C[1] * C[2] * C[3] * C[4], C[2] * C[3] * C[4], C[3] * C[4], C[4], 1};
+  static constexpr int S3 = (C[4] + 7) / 8 * 8;
+  // smallest stride >= C3 * S3 that is 20 mod 32
+  static constexpr int S2 = C[3] * S3 + ((20 - C[3] * S3) % 32 + 32) % 32;
+  static constexpr int S[5] = {C[1] * C[2] * S2, C[2] * S2, S2, S3, 1};
   static constexpr int SIZE = C[0] * S[0];
-  static constexpr int PLANE = S[1];        // cells of dims 2..4: one per staging thread
+  static constexpr int PLANE = C[2] * C[3] * C[4];   // cells of dims 2..4: one per staging thread
   static constexpr int PLANES = C[0] * C[1];
   static_assert(PLANE <= 256, "a plane of the box per workgroup pass");
+  static_assert(S2 % 32 == 20 && S2 >= C[3] * S3, "padded dimension-2 stride");
 };
 
 template <int KIND, class SH>
@@ -1058,6 +1085,11 @@ struct VLds {
 };
 
 #define STAGE_BLOCK 256
+// The loop levels' masses are picked from registers with selects on the
+// (uniform) loop index rather than read from per-thread LDS slots: the sweep
+// is bound by LDS traffic, and the slots would also cost a fifth of the
+// workgroups a CU holds.
+#define STAGE_LL 0
 
 // TAIL: also the largest per-row FP64 tail over the launch into *tailmax.
 template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
@@ -1072,7 +1104,8 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int blo[N];
   VI* box = reinterpret_cast<VI*>(smem);
-  MT* ll = reinterpret_cast<MT*>(smem + ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15)) + threadIdx.x;
+  MT* ll = STAGE_LL ? reinterpret_cast<MT*>(smem + ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15)) + threadIdx.x
+                    : nullptr;
   const int t = threadIdx.x;
   int j[N];
   {
@@ -1098,6 +1131,7 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
   const bool stager = t < BX::PLANE;
   const uint32_t gt = (uint32_t)(t / C3C4) * (uint32_t)P.stride[2] +
                       (uint32_t)((t / BX::C[4]) % BX::C[3]) * (uint32_t)P.stride[3] + (uint32_t)(t % BX::C[4]);
+  const int lt = (t / C3C4) * BX::S[2] + ((t / BX::C[4]) % BX::C[3]) * BX::S[3] + t % BX::C[4];
   const bool free = label[s] == LBL_FREE;
   if (!free) {
     Vout[s] = (label[s] == LBL_ONE) ? VO(1) : VO(0);
@@ -1153,13 +1187,15 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
                        ((uint32_t)(p / BX::C[1]) * (uint32_t)P.stride[0] +
                         (uint32_t)(p % BX::C[1]) * (uint32_t)P.stride[1]) * (uint32_t)sizeof(VI));
 #pragma unroll
-      for (int p = 0; p < BX::PLANES; ++p) box[p * BX::PLANE + t] = v[p];
+      for (int p = 0; p < BX::PLANES; ++p) box[(p / BX::C[1]) * BX::S[0] + (p % BX::C[1]) * BX::S[1] + lt] = v[p];
     }
+    if constexpr (STAGE_LL > 0) {
 #pragma unroll
-    for (int d = 0; d < SH::BL; ++d)
+      for (int d = 0; d < SH::BL; ++d)
 #pragma unroll
-      for (int k = 0; k < SH::LMAX; ++k)
-        if (k < SH::L[d]) ll[(d * SH::LMAX + k) * STAGE_BLOCK] = R.m[d][k];
+        for (int k = 0; k < SH::LMAX; ++k)
+          if (k < SH::L[d]) ll[(d * SH::LMAX + k) * STAGE_LL] = R.m[d][k];
+    }
     __syncthreads();
     if (free) {
       bool in = true;
@@ -1172,9 +1208,9 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
       }
       AT q;
       if (in)
-        q = contract_fixed<0, SH, MT, AT, VLds<VI, BX>, COMP, STAGE_BLOCK>(P, R, vl, lo * (uint32_t)sizeof(VI), 0u, ll);
+        q = contract_fixed<0, SH, MT, AT, VLds<VI, BX>, COMP, STAGE_LL>(P, R, vl, lo * (uint32_t)sizeof(VI), 0u, ll);
       else
-        q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP, STAGE_BLOCK>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
+        q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP, STAGE_LL>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
       if (q > best) {
         best = q;
         arg = u;
@@ -1196,7 +1232,7 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
 template <int KIND, class SH, class MT, class VI>
 static size_t stage_lds_bytes() {
   using BX = StageBox<SH>;
-  return ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) + (size_t)SH::BL * SH::LMAX * sizeof(MT) * STAGE_BLOCK;
+  return ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) + (size_t)SH::BL * SH::LMAX * sizeof(MT) * STAGE_LL;
 }
 
 // ----------------------------------------------- staged planes (7-D)
@@ -1547,6 +1583,24 @@ struct FixedLaunch {
       if (P.L[i] != SH::L[i]) return false;
     return true;
   }
+  // Every step (the tail step included) of a memoised solve runs the staged
+  // box or plane sweep, which read their masses from the tables alone.
+  static bool memo_complete(const DevProblem& P, bool f64) {
+    if (!matches(P) || SH::LMAX > REL_SLOTS) return false;
+    if constexpr (Planed<KIND, SH>::value) {
+      using BX = PlaneBox<SH>;
+      bool ok = !f64 && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0;
+      for (int d = 0; d < 5; ++d) ok = ok && P.count[d] >= BX::C[d];
+      if (ok) return true;
+    }
+    if constexpr (Staged<KIND, SH>::value) {
+      using BX = StageBox<SH>;
+      bool ok = true;
+      for (int d = 0; d < SH::N; ++d) ok = ok && P.count[d] >= BX::C[d] && (d == 0 || P.count[d] % 4 == 0);
+      return ok;
+    }
+    return false;
+  }
   template <class MT, class AT, class VI, class VO, bool COMP>
   static void go(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
                  unsigned long long* tailmax, const void* tables, hipStream_t st) {
@@ -1622,8 +1676,13 @@ struct FixedLaunch {
     const dim3 g((unsigned)((P.rel_entries + 63) / 64)), b(64);
     constexpr int REC = amy_memo_rec(SH::LMAX);
     double* wg = (double*)((char*)tables + memo_wg_offset(P, REC, f64 ? 8 : 4));
-    if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double, REC>), g, b, 0, st, P, (double*)tables, wg);
-    else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float, REC>), g, b, 0, st, P, (float*)tables, wg);
+    if (P.noise != 0) {
+      if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double, REC, true>), g, b, 0, st, P, (double*)tables, wg);
+      else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float, REC, true>), g, b, 0, st, P, (float*)tables, wg);
+    } else {
+      if (f64) hipLaunchKernelGGL((k_memo_build<KIND, SH::N, double, REC, false>), g, b, 0, st, P, (double*)tables, wg);
+      else hipLaunchKernelGGL((k_memo_build<KIND, SH::N, float, REC, false>), g, b, 0, st, P, (float*)tables, wg);
+    }
     return hipGetLastError();
   }
 };
@@ -1735,11 +1794,13 @@ struct FacLaunch {
 // (first argument: the most gathers issued as one unrolled block)
 using ShapeUnicycle = ShapeT<64, 5, 5, 2>;
 using ShapeRoom5 = ShapeT<27, 3, 3, 3, 3, 3>;
+using ShapeRoom5Narrow = ShapeT<16, 2, 2, 2, 2, 2>;  // windows of two cells (noise narrower than a cell)
 using ShapeVehicle7 = ShapeT<27, 2, 2, 3, 3, 3, 3, 3>;
 using ShapeLinear2 = ShapeT<28, 28, 28>;
 #define AMY_FIXED_SHAPES(X)            \
   X(AMY_DYN_UNICYCLE_, ShapeUnicycle)  \
   X(AMY_DYN_ROOM_, ShapeRoom5)         \
+  X(AMY_DYN_ROOM_, ShapeRoom5Narrow)   \
   X(AMY_DYN_VEHICLE7_, ShapeVehicle7)  \
   X(AMY_DYN_AFFINE_, ShapeLinear2)
 
@@ -1796,6 +1857,15 @@ bool amy_fixed_available(const DevProblem& P) {
   if (vbytes >= (1ull << 32)) return false;
 #define X(K, SH) \
   if (FixedLaunch<K, SH>::matches(P)) return true;
+  AMY_FIXED_SHAPES(X)
+#undef X
+  return false;
+}
+
+bool amy_fixed_memo_complete(const DevProblem& P, bool f64) {
+  if ((uint64_t)P.n_x * 8u >= (1ull << 32)) return false;
+#define X(K, SH) \
+  if (FixedLaunch<K, SH>::matches(P)) return FixedLaunch<K, SH>::memo_complete(P, f64);
   AMY_FIXED_SHAPES(X)
 #undef X
   return false;

@@ -34,6 +34,9 @@ hipError_t amy_launch_sweep_stored(const DevProblem& P, SweepKind sk, const void
 // Fixed-window-shape sweep (amy_fixed.hip): available for the instantiated
 // window shapes only.
 bool amy_fixed_available(const DevProblem& P);
+// every step of a solve with memoised tables runs a sweep that reads its
+// masses from those tables alone (so they may hold any noise model's masses)
+bool amy_fixed_memo_complete(const DevProblem& P, bool f64);
 // tables: the memoised tables (P.tables == 2) for the steps without the
 // FP64 tail, or nullptr.
 hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,

@@ -93,7 +93,7 @@ struct Arena {
   }
 };
 
-enum { RQ_QUEUED = 0, RQ_ACTIVE = 1, RQ_DONE = 2, RQ_FAILED = 3 };
+enum { RQ_QUEUED = 0, RQ_ACTIVE = 1, RQ_DONE = 2, RQ_FAILED = 3, RQ_CANCELLED = 4 };
 
 struct Request {
   uint64_t ticket = 0;
@@ -106,6 +106,7 @@ struct Request {
   uint64_t off = 0, bytes = 0, off_v = 0, off_pol = 0;
   int t = 0;  // local step (0 = the step k = T_d)
   bool want_policy = false;
+  bool cancel = false;  // cancellation asked for while active (applied at the next step boundary)
   bool solo = false;  // own sweep launch per step instead of the batched one
   std::vector<double> V;
   std::vector<int16_t> pol;
@@ -150,7 +151,7 @@ struct amy_server {
   bool stop = false;
   std::thread worker;
   // statistics
-  uint64_t submitted = 0, completed = 0, failed = 0, steps = 0;
+  uint64_t submitted = 0, completed = 0, failed = 0, cancelled = 0, steps = 0;
   int max_active = 0;
   double row_updates = 0, busy_s = 0;
   std::vector<double> lat_ms;
@@ -235,7 +236,26 @@ void amy_server::run() {
     {
       std::unique_lock<std::mutex> lk(mu);
       cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+      // cancelled requests leave at this step boundary: the previous
+      // iteration ended with a stream synchronisation, so none of their
+      // work is still in flight
+      bool dropped = false;
+      for (size_t i = 0; i < active.size();) {
+        Request* r = active[i];
+        if (!r->cancel) {
+          ++i;
+          continue;
+        }
+        r->state = RQ_CANCELLED;
+        r->t_done = now_s();
+        arena.release(r->off, r->bytes);
+        active.erase(active.begin() + (ptrdiff_t)i);
+        ++cancelled;
+        dropped = true;
+      }
+      if (dropped) cv_done.notify_all();
       if (stop && active.empty()) break;
+      if (queue.empty() && active.empty()) continue;
       // admission in arrival order while slots and arena space last
       while (!stop && !queue.empty() && (int)active.size() < cfg.max_slots) {
         Request* r = queue.front();
@@ -520,7 +540,7 @@ extern "C" amy_status amy_server_wait(amy_server* s, uint64_t ticket, int32_t ti
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return amy_fail(AMY_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
   Request* r = it->second;
-  auto ready = [&] { return r->state == RQ_DONE || r->state == RQ_FAILED; };
+  auto ready = [&] { return r->state == RQ_DONE || r->state == RQ_FAILED || r->state == RQ_CANCELLED; };
   if (timeout_ms > 0) s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
   else if (timeout_ms < 0) s->cv_done.wait(lk, ready);
   if (!ready()) return amy_fail(AMY_E_NOTREADY, "request %llu not finished", (unsigned long long)ticket);
@@ -529,6 +549,8 @@ extern "C" amy_status amy_server_wait(amy_server* s, uint64_t ticket, int32_t ti
   amy_status st = AMY_OK;
   if (r->state == RQ_FAILED) {
     st = amy_fail(r->err, "%s", r->msg.c_str());
+  } else if (r->state == RQ_CANCELLED) {
+    st = amy_fail(AMY_E_CANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
   } else {
     if (V_host) memcpy(V_host, r->V.data(), r->V.size() * 8);
     if (policy_host && !r->pol.empty()) memcpy(policy_host, r->pol.data(), r->pol.size() * 2);
@@ -543,6 +565,28 @@ extern "C" amy_status amy_server_poll(amy_server* s, uint64_t ticket, double* V_
   return amy_server_wait(s, ticket, 0, V_host, policy_host, info);
 }
 
+extern "C" amy_status amy_server_cancel(amy_server* s, uint64_t ticket) {
+  if (!s) return amy_fail(AMY_E_INVALID, "server is NULL");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return amy_fail(AMY_E_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second;
+  if (r->state == RQ_QUEUED) {
+    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+    r->state = RQ_CANCELLED;
+    r->t_done = now_s();
+    ++s->cancelled;
+    s->cv_done.notify_all();
+    return AMY_OK;
+  }
+  if (r->state == RQ_ACTIVE) {
+    r->cancel = true;  // the worker drops it at the next step boundary
+    s->cv.notify_one();
+    return AMY_OK;
+  }
+  return amy_fail(AMY_E_INVALID, "request %llu has already finished", (unsigned long long)ticket);
+}
+
 extern "C" amy_status amy_server_get_stats(amy_server* s, amy_server_stats* out) {
   if (!s || !out) return amy_fail(AMY_E_INVALID, "NULL argument");
   std::lock_guard<std::mutex> g(s->mu);
@@ -550,6 +594,7 @@ extern "C" amy_status amy_server_get_stats(amy_server* s, amy_server_stats* out)
   out->submitted = s->submitted;
   out->completed = s->completed;
   out->failed = s->failed;
+  out->cancelled = s->cancelled;
   out->queued = (int32_t)s->queue.size();
   out->active = (int32_t)s->active.size();
   out->max_active = s->max_active;
@@ -578,7 +623,7 @@ extern "C" amy_status amy_server_get_stats(amy_server* s, amy_server_stats* out)
 extern "C" amy_status amy_server_reset_stats(amy_server* s) {
   if (!s) return amy_fail(AMY_E_INVALID, "server is NULL");
   std::lock_guard<std::mutex> g(s->mu);
-  s->completed = s->failed = s->steps = 0;
+  s->completed = s->failed = s->cancelled = s->steps = 0;
   s->submitted = s->reqs.size();
   s->row_updates = s->busy_s = 0;
   s->max_active = (int)s->active.size();

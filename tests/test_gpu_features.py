@@ -61,6 +61,13 @@ def _room_patch(**kw):
     return p.with_(lo=lo, h=h, count=cnt, horizon=5, name="room-patch", **kw)
 
 
+def _room8(**kw):
+    # whole 1 x 4 x 4 x 4 x 4 tiles: the steps read memoised tables and stage V boxes
+    p = W.room5d()
+    lo, h, cnt = W.tiling((19.6,) * 5, (20.4,) * 5, (8,) * 5)
+    return p.with_(lo=lo, h=h, count=cnt, horizon=5, name="room-8^5", **kw)
+
+
 def _lin(**kw):
     p = W.linear2d(cells=37, precision="fp32", mode="otf")
     kw.setdefault("horizon", 6)
@@ -94,6 +101,14 @@ CASES = {
     "room-uniform-fp32": lambda: _room_patch(noise="uniform", noise_a=(-0.06,) * 5, noise_b=(0.06,) * 5),
     "room-exponential-fp64": lambda: _room_patch(noise="exponential", noise_a=(30.0,) * 5, cutoff=1e-2,
                                                  precision="fp64"),
+    # the other noise models through memoised tables (two-cell windows)
+    "room8-beta-fp32-memo": lambda: _room8(noise="beta", noise_a=(-0.05,) * 5, noise_b=(0.05,) * 5,
+                                           noise_alpha=(2.0,) * 5, noise_beta=(2.0,) * 5),
+    "room8-uniform-fp64-memo": lambda: _room8(noise="uniform", noise_a=(-0.06,) * 5, noise_b=(0.06,) * 5,
+                                              precision="fp64"),
+    "room8-beta-fp32-memo-coupled": lambda: _room8(noise="beta", noise_a=(-0.05,) * 5, noise_b=(0.05,) * 5,
+                                                   noise_alpha=(2.0,) * 5, noise_beta=(3.0,) * 5,
+                                                   params=(0.25, 0.005, 0.01, -1.0, 50.0)),
     # intersect window and multiplicative noise (Eq. 3.2, Sec. 6.2)
     "unicycle-intersect-fp32": lambda: _uni_patch(window="intersect", horizon=3),
     "unicycle-intersect-fp64": lambda: _uni_patch(window="intersect", precision="fp64", horizon=3),
@@ -128,6 +143,14 @@ def test_plain_problems_keep_the_compiled_sweeps():
     assert A.query(W.unicycle3d())["variant"] == "factored"
     assert A.query(W.room5d())["variant"] == "fixed"
     assert A.query(W.room5d().with_(window="intersect"))["variant"] in ("lanes", "group16", "group64")
+    # other noise models: the compiled shape when every step reads memoised
+    # tables (whole staged tiles), the run-time-window sweeps otherwise
+    beta = dict(noise="beta", noise_a=(-0.05,) * 5, noise_b=(0.05,) * 5, noise_alpha=(2.0,) * 5,
+                noise_beta=(2.0,) * 5)
+    assert A.query(W.room5d().with_(**beta))["variant"] == "fixed"
+    assert A.query(_room8(**beta))["variant"] == "fixed"
+    assert A.query(_room_patch(**beta))["variant"] in ("lanes", "group16", "group64")
+    assert A.query(_room8(multiplicative=True))["variant"] in ("lanes", "group16", "group64")
     assert A.query(_lin_dist())["variant"] in ("lanes", "group16", "group64")
 
 

@@ -130,3 +130,36 @@ def test_server_errors():
         assert srv.stats()["failed"] == 1
     with pytest.raises(AmyError):
         A.Server(hbm_budget_bytes=1024, max_slots=2)
+
+
+def test_server_cancellation(orc):
+    """A queued request leaves the queue at once, a running one at the next
+    step boundary; both answer E_CANCELLED and free their arena space, and
+    the request behind them finishes with the solo result."""
+    import paper_2005_06191_amd as A
+    from paper_2005_06191_amd.binding import E_CANCELLED, E_INVALID, AmyError
+    long = W.room5d(horizon=400)  # a few hundred ms on the device
+    quick = W.linear2d(cells=30, precision="fp32", mode="otf", horizon=4)
+    say("[server] cancellation: one queued, one running")
+    with A.Server(hbm_budget_bytes=1 << 30, max_slots=1) as srv:
+        t_long = srv.submit(long)
+        t_q1 = srv.submit(quick)
+        t_q2 = srv.submit(quick)
+        srv.cancel(t_q1)  # queued behind the long request (one slot)
+        t0 = time.time()
+        while srv.stats()["active"] < 1 and time.time() - t0 < 10.0:
+            time.sleep(0.001)
+        srv.cancel(t_long)  # running
+        for t in (t_q1, t_long):
+            with pytest.raises(AmyError) as e:
+                srv.wait(t, timeout_ms=60000)
+            assert e.value.status == E_CANCELLED
+        V, _, info = srv.wait(t_q2, timeout_ms=60000)
+        st = srv.stats()
+        # released tickets are unknown to the server
+        with pytest.raises(AmyError) as e:
+            srv.cancel(t_q2)
+        assert e.value.status == E_INVALID
+    _check_against_solo_and_oracle(orc, quick, V, None, info)
+    assert st["cancelled"] == 2 and st["completed"] == 1 and st["failed"] == 0
+    assert st["hbm_in_use"] == 0 and st["active"] == 0 and st["queued"] == 0

@@ -900,6 +900,73 @@ __global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict_
   wg[2 * (int64_t)e + 1] = gm;
 }
 
+// FP64 row tails alone from the memoised kept-window and grid masses (wg,
+// filled by k_memo_build), for the first step of a solve whose sweep forms
+// none (the factored sweep on shared relative tables).  The memo entries
+// hold the per-state code's masses for the state's own context, and each
+// row multiplies them in dimension order as the per-state path does, so
+// the max is that path's, bit for bit, at a few loads per row instead of
+// the per-state FP64 means, windows and erfc's.  A state's entries (one per
+// input-digit combination of each dimension, sum_i rcount_i of them) are
+// first copied into its own LDS column with independent loads, so the input
+// loop waits on no memory.
+#define TAIL_MEMO_BLOCK 64
+template <int N>
+__global__ void __launch_bounds__(TAIL_MEMO_BLOCK) k_tail_memo(DevProblem P, const uint8_t* __restrict__ label,
+                                                               const double* __restrict__ wg,
+                                                               unsigned long long* __restrict__ tailmax) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double2* ent = reinterpret_cast<double2*>(smem) + threadIdx.x;  // [entry][lane]
+  const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * TAIL_MEMO_BLOCK + threadIdx.x;
+  double tmax = 0.0;
+  if (s < (uint32_t)P.n_x && label[s] == LBL_FREE) {
+    int j[N];
+    uint32_t r = s;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      j[i] = (int)(r % (uint32_t)P.count[i]);
+      r /= (uint32_t)P.count[i];
+    }
+    int eoff[N];
+    int off = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      int v = 0;
+      for (int k = 0; k < P.mctx_n[i]; ++k) {
+        int jk = j[0];
+#pragma unroll
+        for (int d = 1; d < N; ++d)
+          if (d == P.mctx[i][k]) jk = j[d];
+        v += jk * P.mmult[i][k];
+      }
+      const double2* src = reinterpret_cast<const double2*>(wg) + ((int64_t)P.rel_off[i] + (int64_t)v * P.rcount[i]);
+      const int rc = P.rcount[i];
+#pragma unroll 4
+      for (int c = 0; c < rc; ++c) ent[(off + c) * TAIL_MEMO_BLOCK] = src[c];
+      eoff[i] = off;
+      off += rc;
+    }
+    InputWalk iw;
+    iw.reset();
+    for (int u = 0; u < P.n_u; ++u) {
+      double win = 1.0, grid = 1.0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < AMY_MAXI; ++k) c += iw.dig[k] * P.rmult[i][k];
+        const double2 w2 = ent[(eoff[i] + c) * TAIL_MEMO_BLOCK];
+        win *= w2.x;
+        grid *= w2.y;
+      }
+      tmax = fmax(tmax, grid - win);
+      iw.next(P);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+  if ((threadIdx.x & 63) == 0 && tmax > 0.0) atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+}
+
 // Byte offset of the memoised tables' FP64 window and grid masses.
 __host__ __device__ inline uint64_t memo_wg_offset(const DevProblem& P, int rec, uint64_t msz) {
   return ((uint64_t)P.rel_entries * (uint64_t)rec * msz + 255) & ~255ull;
@@ -1880,6 +1947,29 @@ hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void*
   AMY_FIXED_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+size_t amy_tail_memo_lds(const DevProblem& P) {
+  size_t ne = 0;
+  for (int i = 0; i < P.n; ++i) ne += (size_t)P.rcount[i];
+  return ne * 16 * TAIL_MEMO_BLOCK;
+}
+
+hipError_t amy_launch_tail_memo(const DevProblem& P, bool f64, const uint8_t* label, const void* tables,
+                                unsigned long long* tailmax, hipStream_t st) {
+  int lmax = 1;
+  for (int i = 0; i < P.n; ++i) lmax = P.L[i] > lmax ? P.L[i] : lmax;
+  const double* wg = (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(lmax), f64 ? 8 : 4));
+  const dim3 g((unsigned)((P.n_x + TAIL_MEMO_BLOCK - 1) / TAIL_MEMO_BLOCK)), b(TAIL_MEMO_BLOCK);
+  const size_t lds = amy_tail_memo_lds(P);
+  switch (P.n) {
+#define T(NN) \
+  case NN: hipLaunchKernelGGL((k_tail_memo<NN>), g, b, lds, st, P, label, wg, tailmax); break;
+    T(1) T(2) T(3) T(4) T(5) T(6) T(7) T(8)
+#undef T
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t amy_launch_memo_build(const DevProblem& P, bool f64, void* tables, hipStream_t st) {

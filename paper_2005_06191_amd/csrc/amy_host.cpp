@@ -647,8 +647,9 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
     // one lane per state while its tables leave room for >= 6 waves per CU
     // and the window is small; otherwise lanes share a state's window
     const bool lanes_light = lanes_ok && pl->dev.lds_bytes_tail <= 24 * 1024 && pl->W < 1024;
-    // few states with many rows each: one wave per state keeps the GPU busy
-    const bool few_states = (pl->dev.n_x + 63) / 64 < 1024 && pl->dev.n_u >= 16;
+    // few states with enough rows each to fill a wave's lanes (inputs times
+    // disturbance points): one wave per state keeps the GPU busy
+    const bool few_states = (pl->dev.n_x + 63) / 64 < 1024 && pl->dev.n_rows >= 64;
     if (fac_ok) v = AMY_VARIANT_FACTORED;
     else if (fixed_ok) v = AMY_VARIANT_FIXED;
     else if (inputs_ok && few_states) v = AMY_VARIANT_INPUTS;
@@ -682,6 +683,25 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
     if (budget && pl->ws_bytes > budget)
       return amy_fail(AMY_E_NOMEM, "workspace %llu B exceeds budget %llu B",
                       (unsigned long long)pl->ws_bytes, (unsigned long long)budget);
+  }
+  // the factored sweep forms no row tails: its first step takes them from
+  // memoised kept-window and grid masses when those tables can be planned
+  pl->tail_memo = false;
+  if (pl->dev.variant == AMY_VARIANT_FACTORED && pl->dev.tables == 1) {
+    DevProblem q = pl->dev;
+    if (plan_memo(p, q)) {
+      q.tables = 2;
+      int lmax = 1;
+      for (int i = 0; i < q.n; ++i) lmax = q.L[i] > lmax ? q.L[i] : lmax;
+      const uint64_t msz = pl->f64 ? 8 : 4, ne = (uint64_t)q.rel_entries;
+      const uint64_t bytes = ((ne * (uint64_t)amy_memo_rec(lmax) * msz + 255) & ~255ull) + ((ne * 16 + 255) & ~255ull);
+      if ((!budget || pl->ws_bytes + bytes <= budget) && amy_tail_memo_lds(q) <= 64 * 1024) {
+        pl->tail_memo = true;
+        pl->tail_dev = q;
+        pl->off_tailtab = pl->ws_bytes;
+        pl->ws_bytes += bytes;
+      }
+    }
   }
   plan_group(pl, v == AMY_VARIANT_GROUP64 ? 64 : 16);
   if (v != AMY_VARIANT_GROUP16 && v != AMY_VARIANT_GROUP64) pl->dev.grp_g = 1;
@@ -781,10 +801,18 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
                               want_tail ? tailmax : nullptr, st)) != hipSuccess)
       return amy_hip_fail(e, "build kernel");
   }
+  // the factored first step's tails from memoised tables, built here
+  const bool tail_tab = want_tail && horizon > 0 && !stored && pl.tail_memo;
+  if (tail_tab) {
+    void* tab = base + pl.off_tailtab;
+    if ((e = amy_launch_memo_build(pl.tail_dev, pl.f64, tab, st)) != hipSuccess ||
+        (e = amy_launch_tail_memo(pl.tail_dev, pl.f64, label, tab, tailmax, st)) != hipSuccess)
+      return amy_hip_fail(e, "tail tables");
+  }
   if (tm) hipEventRecord(tm->ev[1], st);
   for (int k = horizon; k >= 1; --k) {
     if (tm && k == 1) hipEventRecord(tm->ev[2], st);
-    if ((e = amy_enqueue_step(pl, st, ws, V_out, pol, horizon, k, want_tail)) != hipSuccess)
+    if ((e = amy_enqueue_step(pl, st, ws, V_out, pol, horizon, k, want_tail && !tail_tab)) != hipSuccess)
       return amy_hip_fail(e, "sweep kernel");
     if (tm && k == horizon) hipEventRecord(tm->ev[5], st);
   }

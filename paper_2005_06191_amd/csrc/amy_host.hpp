@@ -18,6 +18,12 @@ struct Plan {
   uint64_t off_label, off_v0, off_v1, off_tail, off_T, off_org;
   uint64_t off_rel;  // factored sweep's shared relative tables (dev.rel_entries > 0)
   uint64_t stored_bytes, ws_bytes;
+  // the factored solve's first-step FP64 tails from memoised tables: the
+  // problem planned for those tables (its rel_* fields describe them) and
+  // their place in the workspace
+  bool tail_memo = false;
+  DevProblem tail_dev;
+  uint64_t off_tailtab = 0;
 };
 
 // ev[0] start, ev[1] sweeps begin, ev[5] after the first sweep (k = T_d),

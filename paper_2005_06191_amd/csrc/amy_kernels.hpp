@@ -43,6 +43,12 @@ hipError_t amy_launch_sweep_fixed(const DevProblem& P, SweepKind sk, const void*
                                   const uint8_t* label, int16_t* pol, unsigned long long* tailmax,
                                   const void* tables, hipStream_t st);
 hipError_t amy_launch_memo_build(const DevProblem& P, bool f64, void* tables, hipStream_t st);
+// The first step's FP64 row tails from memoised tables (P planned for them,
+// tables built by amy_launch_memo_build with the same P).
+// LDS of that pass per workgroup (every dimension's entries of a state, per lane)
+size_t amy_tail_memo_lds(const DevProblem& P);
+hipError_t amy_launch_tail_memo(const DevProblem& P, bool f64, const uint8_t* label, const void* tables,
+                                unsigned long long* tailmax, hipStream_t st);
 // Factored compiled-shape sweep (inputs sharing the outer dimensions' windows).
 // rel: the shared relative tables (when P.rel_entries > 0) for the steps
 // without the FP64 tail; the tail step builds its tables per state.

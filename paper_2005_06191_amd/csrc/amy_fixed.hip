@@ -908,15 +908,15 @@ __global__ void __launch_bounds__(64) k_memo_build(DevProblem P, MT* __restrict_
 // the max is that path's, bit for bit, at a few loads per row instead of
 // the per-state FP64 means, windows and erfc's.  A state's entries (one per
 // input-digit combination of each dimension, sum_i rcount_i of them) are
-// first copied into its own LDS column with independent loads, so the input
-// loop waits on no memory.
+// first loaded into its own LDS column, so the input loop waits on no memory.
 #define TAIL_MEMO_BLOCK 64
 template <int N>
 __global__ void __launch_bounds__(TAIL_MEMO_BLOCK) k_tail_memo(DevProblem P, const uint8_t* __restrict__ label,
                                                                const double* __restrict__ wg,
                                                                unsigned long long* __restrict__ tailmax) {
   extern __shared__ __align__(16) unsigned char smem[];
-  double2* ent = reinterpret_cast<double2*>(smem) + threadIdx.x;  // [entry][lane]
+  double2* ent0 = reinterpret_cast<double2*>(smem);  // [entry][lane]
+  double2* ent = ent0 + threadIdx.x;
   const uint32_t s = xcd_block(blockIdx.x, gridDim.x) * TAIL_MEMO_BLOCK + threadIdx.x;
   double tmax = 0.0;
   if (s < (uint32_t)P.n_x && label[s] == LBL_FREE) {
@@ -928,6 +928,7 @@ __global__ void __launch_bounds__(TAIL_MEMO_BLOCK) k_tail_memo(DevProblem P, con
       r /= (uint32_t)P.count[i];
     }
     int eoff[N];
+    const double2* src[N];
     int off = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -939,13 +940,22 @@ __global__ void __launch_bounds__(TAIL_MEMO_BLOCK) k_tail_memo(DevProblem P, con
           if (d == P.mctx[i][k]) jk = j[d];
         v += jk * P.mmult[i][k];
       }
-      const double2* src = reinterpret_cast<const double2*>(wg) + ((int64_t)P.rel_off[i] + (int64_t)v * P.rcount[i]);
-      const int rc = P.rcount[i];
-#pragma unroll 4
-      for (int c = 0; c < rc; ++c) ent[(off + c) * TAIL_MEMO_BLOCK] = src[c];
+      src[i] = reinterpret_cast<const double2*>(wg) + ((int64_t)P.rel_off[i] + (int64_t)v * P.rcount[i]);
       eoff[i] = off;
-      off += rc;
+      off += P.rcount[i];
     }
+    // every entry straight from memory into the state's LDS column (the
+    // load-to-LDS form writes lane l's 16 bytes at the given wave-uniform
+    // base + 16 l, which is the [entry][lane] layout), all in flight at once
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int rc = P.rcount[i];
+      for (int c = 0; c < rc; ++c)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src[i] + c),
+                                         (__attribute__((address_space(3))) void*)(ent0 + (eoff[i] + c) * TAIL_MEMO_BLOCK),
+                                         16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the loads have landed in LDS
     InputWalk iw;
     iw.reset();
     for (int u = 0; u < P.n_u; ++u) {

@@ -83,12 +83,30 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
     prev[i] = __builtin_nan("");
     o[i] = 0;
   }
-  // lane space: the dimensions from nout on, flattened (last fastest)
+  // lane space: the dimensions from nout on, flattened (last fastest); a
+  // lane's first index gl and the stride G as mixed-radix digits, so the
+  // lane steps through its indices with carries instead of divisions
   const int nout = P.grp_nout;
   int ls = 1;
 #pragma unroll
   for (int i = 0; i < N; ++i)
     if (i >= nout) ls *= P.L[i];
+  int kin0[N], kinc[N];
+  {
+    int rr = gl, rg = G;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      if (i >= nout) {
+        kin0[i] = rr % P.L[i];
+        rr /= P.L[i];
+        kinc[i] = rg % P.L[i];
+        rg /= P.L[i];
+      } else {
+        kin0[i] = 0;
+        kinc[i] = 0;
+      }
+    }
+  }
   InputWalk iw;
   iw.reset();
   AT best = AT(-1), qmin = AT(0);
@@ -123,20 +141,11 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
     for (int i = 0; i < N; ++i) base += (int64_t)o[i] * P.stride[i];
     AT acc = AT(0), cmp = AT(0);
     if (active) {
-      for (int j = gl; j < ls; j += G) {
-        int kin[N];
-        AT mi = AT(1);
-        int rr = j;
+      int kin[N];
 #pragma unroll
-        for (int i = N - 1; i >= 0; --i) {
-          if (i >= nout) {
-            const int k = rr % P.L[i];
-            rr /= P.L[i];
-            kin[i] = k;
-          } else {
-            kin[i] = 0;
-          }
-        }
+      for (int i = 0; i < N; ++i) kin[i] = kin0[i];
+      for (int j = gl; j < ls; j += G) {
+        AT mi = AT(1);
 #pragma unroll
         for (int i = 0; i < N; ++i)
           if (i >= nout) mi = mi * AT(tab[P.goff[i] + kin[i]]);
@@ -148,6 +157,16 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
           acc = s2;
         } else {
           acc = fma_(mi, sj, acc);
+        }
+        // kin += the digits of G (each digit sum stays below 2 L_i)
+        int carry = 0;
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+          if (i >= nout) {
+            const int k = kin[i] + kinc[i] + carry;
+            carry = k >= P.L[i] ? 1 : 0;
+            kin[i] = carry ? k - P.L[i] : k;
+          }
         }
       }
     }

@@ -1870,12 +1870,14 @@ struct FacLaunch {
 // room ring, 7-D vehicle).
 // (first argument: the most gathers issued as one unrolled block)
 using ShapeUnicycle = ShapeT<64, 5, 5, 2>;
+using ShapeUnicycleWide = ShapeT<64, 6, 6, 3>;  // the same noise with the intersect window rule
 using ShapeRoom5 = ShapeT<27, 3, 3, 3, 3, 3>;
 using ShapeRoom5Narrow = ShapeT<16, 2, 2, 2, 2, 2>;  // windows of two cells (noise narrower than a cell)
 using ShapeVehicle7 = ShapeT<27, 2, 2, 3, 3, 3, 3, 3>;
 using ShapeLinear2 = ShapeT<28, 28, 28>;
 #define AMY_FIXED_SHAPES(X)            \
   X(AMY_DYN_UNICYCLE_, ShapeUnicycle)  \
+  X(AMY_DYN_UNICYCLE_, ShapeUnicycleWide) \
   X(AMY_DYN_ROOM_, ShapeRoom5)         \
   X(AMY_DYN_ROOM_, ShapeRoom5Narrow)   \
   X(AMY_DYN_VEHICLE7_, ShapeVehicle7)  \

@@ -599,16 +599,20 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   // rows without a disturbance; everything else runs the run-time-window ones
   const bool plain = pl->dev.pd == 0 && pl->dev.noise == AMY_NOISE_NORMAL && pl->dev.wrule == AMY_WINDOW_CENTRE &&
                      !pl->dev.mult;
+  // the compiled shapes' own tables are additive normal masses over the
+  // window either rule gives; only the factored sweep's shared relative
+  // tables assume the centre rule
+  const bool normal_masses = pl->dev.pd == 0 && pl->dev.noise == AMY_NOISE_NORMAL && !pl->dev.mult;
   // the other noise models and the intersect window (additive noise, no
   // disturbance) run a compiled shape when every step of the solve reads its
   // masses from memoised tables, which are built with the general path
   bool memo_only_ok = false;
-  if (!plain && !user && pl->dev.pd == 0 && !pl->dev.mult && mode == AMY_MODE_OTF &&
+  if (!normal_masses && !user && pl->dev.pd == 0 && !pl->dev.mult && mode == AMY_MODE_OTF &&
       amy_fixed_memo_complete(pl->dev, pl->f64)) {
     DevProblem q = pl->dev;
     memo_only_ok = plan_memo(p, q);
   }
-  const bool fixed_ok = lanes_ok && (plain ? amy_fixed_available(pl->dev) : memo_only_ok);
+  const bool fixed_ok = lanes_ok && (normal_masses ? amy_fixed_available(pl->dev) : memo_only_ok);
   const bool fac_ok = fixed_ok && plain && mode == AMY_MODE_OTF && amy_fac_available(pl->dev);
   int64_t sum_l = 0;
   for (int i = 0; i < pl->dev.n; ++i) sum_l += pl->dev.L[i];

@@ -236,3 +236,20 @@ def test_inputs_variant_full_robot_chained(orc):
     assert float(np.abs(V[st] - Vr).max()) <= TOL_FP32
     clear = gap > 2 * TOL_FP32
     assert np.array_equal(pol[0][st][clear], pr[clear])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_intersect_compiled_shape_is_bitwise_lanes(prec):
+    """With the intersect rule the unicycle's windows are 6 x 6 x 3, a
+    compiled shape: AUTO runs it there (memoised tables), and its rows are
+    bitwise those of the run-time-window LANES sweep."""
+    import paper_2005_06191_amd as A
+    p = CASES[f"unicycle-intersect-{prec}"]()
+    say(f"[intersect fixed vs lanes] {prec}")
+    assert A.query(p)["variant"] == "fixed"
+    a = A.solve(p)
+    b = A.solve(p.with_(variant="lanes"))
+    assert a.info["variant"] == "fixed" and b.info["variant"] == "lanes"
+    assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())
+    assert np.array_equal(a.policy.cpu().numpy(), b.policy.cpu().numpy())
+    assert a.info["max_row_tail"] == b.info["max_row_tail"]

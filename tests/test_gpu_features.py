@@ -68,6 +68,21 @@ def _room8(**kw):
     return p.with_(lo=lo, h=h, count=cnt, horizon=5, name="room-8^5", **kw)
 
 
+def _vehicle_planes(**kw):
+    # whole yaw-rate / slip-angle planes: the steps read memoised tables and stage planes of V
+    p = W.vehicle7d()
+    return p.with_(lo=(-2.5, -2.5, -0.15, -0.75, -0.225, -0.4, -0.04), count=(2, 2, 3, 3, 6, 8, 8),
+                   horizon=4, u_count=(3, 3), name="vehicle7-planes", **kw)
+
+
+def _vehicle_uniform(**kw):
+    # uniform noise whose windows are the compiled vehicle shape 2 x 2 x 3^5
+    # (half-widths 0.45 h in the positions, 0.9 h elsewhere: supports meeting 2 and 3 cells)
+    h = W.vehicle7d().h
+    a = tuple((0.45 if i < 2 else 0.9) * h[i] for i in range(7))
+    return _vehicle_planes(noise="uniform", noise_a=tuple(-x for x in a), noise_b=a, **kw)
+
+
 def _lin(**kw):
     p = W.linear2d(cells=37, precision="fp32", mode="otf")
     kw.setdefault("horizon", 6)
@@ -109,6 +124,7 @@ CASES = {
     "room8-beta-fp32-memo-coupled": lambda: _room8(noise="beta", noise_a=(-0.05,) * 5, noise_b=(0.05,) * 5,
                                                    noise_alpha=(2.0,) * 5, noise_beta=(3.0,) * 5,
                                                    params=(0.25, 0.005, 0.01, -1.0, 50.0)),
+    "vehicle7-planes-uniform-fp32-memo": lambda: _vehicle_uniform(),
     # intersect window and multiplicative noise (Eq. 3.2, Sec. 6.2)
     "unicycle-intersect-fp32": lambda: _uni_patch(window="intersect", horizon=3),
     "unicycle-intersect-fp64": lambda: _uni_patch(window="intersect", precision="fp64", horizon=3),
@@ -151,6 +167,10 @@ def test_plain_problems_keep_the_compiled_sweeps():
     assert A.query(_room8(**beta))["variant"] == "fixed"
     assert A.query(_room_patch(**beta))["variant"] in ("lanes", "group16", "group64")
     assert A.query(_room8(multiplicative=True))["variant"] in ("lanes", "group16", "group64")
+    q = A.query(_vehicle_uniform())
+    assert q["variant"] == "fixed" and q["window"][:7] == [2, 2, 3, 3, 3, 3, 3]
+    # the FP64 vehicle keeps the gather sweep, which computes normal masses only
+    assert A.query(_vehicle_uniform(precision="fp64"))["variant"] in ("lanes", "group16", "group64")
     assert A.query(_lin_dist())["variant"] in ("lanes", "group16", "group64")
 
 

@@ -522,6 +522,22 @@ __device__ __forceinline__ int combo_index(const DevProblem& P, int i, const Inp
   return c;
 }
 
+// ------------------------------------------------------- tail reduction
+
+// Max of the wave's row tails into *tailmax (non-negative doubles order as
+// their bits): one lane per wave updates it, and only when its value exceeds
+// what the location already holds.  Every wave of a launch targets the same
+// address, so unconditional atomics serialise there (one per wave: about
+// 12 ns each, 0.1 ms for the unicycle's 9,375 waves); a stale read can only
+// be lower than the location, so no needed update is skipped.
+__device__ __forceinline__ void wave_max_to(double tmax, unsigned long long* tailmax) {
+  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
+  if ((threadIdx.x & 63) == 0 && tmax > 0.0) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(tmax);
+    if (b > __hip_atomic_load(tailmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(tailmax, b);
+  }
+}
+
 // ------------------------------------------------------------- contraction
 
 // sum over the window of prod_i t_i[k_i] * V[base + sum_i k_i stride_i],
@@ -548,10 +564,12 @@ __device__ __forceinline__ AT contract(const DevProblem& P, const MT* __restrict
       for (int j = 0; j < 4; ++j) acc = fma_(AT(m[j]), v[j], acc);
     }
   }
-  for (int k = k0; k < L; ++k) {
+  const int64_t step = D == N - 1 ? 1 : (int64_t)P.stride[D];
+  int64_t o = base + (int64_t)k0 * step;  // slot k's offset, stepped rather than multiplied
+  for (int k = k0; k < L; ++k, o += step) {
     AT inner;
-    if constexpr (D == N - 1) inner = AT(V[base + k]);
-    else inner = contract<D + 1, N, MT, AT, VT, COMP>(P, t, ts, toff, V, base + (int64_t)k * P.stride[D]);
+    if constexpr (D == N - 1) inner = AT(V[o]);
+    else inner = contract<D + 1, N, MT, AT, VT, COMP>(P, t, ts, toff, V, o);
     if constexpr (COMP && D == 0) {
       const AT y = AT(td[k * ts]) * inner - c;
       const AT s2 = acc + y;

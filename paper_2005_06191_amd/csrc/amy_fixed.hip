@@ -305,9 +305,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fixed(DevProblem P, const V
     }
   }
   if constexpr (TAIL) {
-    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-    if ((threadIdx.x & 63) == 0 && tmax > 0.0)
-      atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+    wave_max_to(tmax, tailmax);
   }
 }
 
@@ -389,8 +387,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_tail_cached(DevProblem P, const u
       iw.next(P);
     }
   }
-  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-  if ((threadIdx.x & 63) == 0 && tmax > 0.0) atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+  wave_max_to(tmax, tailmax);
 }
 
 // ---------------------------------------------------------------- factored
@@ -604,9 +601,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_fac(DevProblem P, const VI*
     }
   }
   if constexpr (TAIL) {
-    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-    if ((threadIdx.x & 63) == 0 && tmax > 0.0)
-      atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+    wave_max_to(tmax, tailmax);
   }
 }
 
@@ -956,25 +951,40 @@ __global__ void __launch_bounds__(TAIL_MEMO_BLOCK) k_tail_memo(DevProblem P, con
                                          16, 0, 0);
     }
     __builtin_amdgcn_s_waitcnt(0);  // the loads have landed in LDS
-    InputWalk iw;
-    iw.reset();
+    // walk the inputs (last digit fastest) keeping each dimension's entry
+    // index e_i = eoff_i + sum_k dig_k rmult_ik up to date with adds
+    int dig[AMY_MAXI], e[N];
+#pragma unroll
+    for (int k = 0; k < AMY_MAXI; ++k) dig[k] = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) e[i] = eoff[i];
     for (int u = 0; u < P.n_u; ++u) {
       double win = 1.0, grid = 1.0;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
-        int c = 0;
-#pragma unroll
-        for (int k = 0; k < AMY_MAXI; ++k) c += iw.dig[k] * P.rmult[i][k];
-        const double2 w2 = ent[(eoff[i] + c) * TAIL_MEMO_BLOCK];
+        const double2 w2 = ent[e[i] * TAIL_MEMO_BLOCK];
         win *= w2.x;
         grid *= w2.y;
       }
       tmax = fmax(tmax, grid - win);
-      iw.next(P);
+      bool carry = true;
+#pragma unroll
+      for (int k = AMY_MAXI - 1; k >= 0; --k) {
+        if (carry && k < P.m) {
+          if (++dig[k] >= P.ucount[k]) {
+            dig[k] = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) e[i] -= (P.ucount[k] - 1) * P.rmult[i][k];
+          } else {
+            carry = false;
+#pragma unroll
+            for (int i = 0; i < N; ++i) e[i] += P.rmult[i][k];
+          }
+        }
+      }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-  if ((threadIdx.x & 63) == 0 && tmax > 0.0) atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+  wave_max_to(tmax, tailmax);
 }
 
 // Byte offset of the memoised tables' FP64 window and grid masses.
@@ -1300,9 +1310,7 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
     if (pol) pol[s] = (int16_t)arg;
   }
   if constexpr (TAIL) {
-    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-    if ((threadIdx.x & 63) == 0 && tmax > 0.0)
-      atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+    wave_max_to(tmax, tailmax);
   }
 }
 
@@ -1482,9 +1490,7 @@ __global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const
     if (pol) pol[s] = (int16_t)arg;
   }
   if constexpr (TAIL) {
-    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-    if ((threadIdx.x & 63) == 0 && tmax > 0.0)
-      atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+    wave_max_to(tmax, tailmax);
   }
 }
 

@@ -86,13 +86,6 @@ __global__ void __launch_bounds__(256) k_init(DevProblem P, uint8_t* __restrict_
 
 // ------------------------------------------------------------------ tail
 
-__device__ __forceinline__ void wave_max_to(double tmax, unsigned long long* tailmax) {
-  // wave max, then one atomic per wave (non-negative doubles order as their bits)
-  for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-  if ((threadIdx.x & 63) == 0 && tmax > 0.0)
-    atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
-}
-
 // Stand-alone tail pass (when no sweep computes it: T_d = 0, and the
 // batched launches): max over rows (x free, all u) of
 // P_mu(grid box) - P_mu(kept window), FP64.

@@ -32,21 +32,22 @@ __device__ __forceinline__ AT gsum(const DevProblem& P, int nout, const MT* __re
   } else {
     if (D < nout) {
       const MT* td = t + P.goff[D];
+      const int64_t sd = P.stride[D];
       AT acc = AT(0);
       int k = 0;
+      int64_t o = off;  // offset of slot k (stepped, not multiplied)
       if constexpr (D >= N - 2) {
         // the last levels: four sub-sums (gathers) in flight, added in slot order
         for (; k + 4 <= P.L[D]; k += 4) {
           AT in[4];
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            in[j] = gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, off + (int64_t)(k + j) * P.stride[D]);
+          for (int j = 0; j < 4; ++j) in[j] = gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, o + j * sd);
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc = fma_(AT(td[k + j]), in[j], acc);
+          o += 4 * sd;
         }
       }
-      for (; k < P.L[D]; ++k)
-        acc = fma_(AT(td[k]), gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, off + (int64_t)k * P.stride[D]), acc);
+      for (; k < P.L[D]; ++k, o += sd) acc = fma_(AT(td[k]), gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, o), acc);
       return acc;
     }
     return gsum<D + 1, N, MT, AT, VT>(P, nout, t, kin, V, off + (int64_t)kin[D] * P.stride[D]);
@@ -191,7 +192,6 @@ __device__ __forceinline__ void sweep_group(const DevProblem& P, uint32_t tile, 
     if (pol) pol[s] = (int16_t)arg;
   }
   if constexpr (TAIL) {
-    for (int off = 32; off > 0; off >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, off));
-    if (lane == 0 && tmax > 0.0) atomicMax(tailmax, (unsigned long long)__double_as_longlong(tmax));
+    wave_max_to(tmax, tailmax);
   }
 }

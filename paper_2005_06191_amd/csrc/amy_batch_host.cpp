@@ -36,6 +36,8 @@ int amy_lds_blocks_per_cu(int dev, size_t lds) {
 // register budget (and so its occupancy) at that of those two.  The
 // compiled-shape variants become LANES, GROUP16 becomes GROUP64, and stored
 // rows are walked 64 states per tile whatever the variant.
+static const int BATCH_LANES_LDS = 8 * 1024;  // bytes of per-lane tables a batched LANES system may take
+
 amy_status amy_batch_normalise(const amy_problem* p, Plan* pl) {
   DevProblem& D = pl->dev;
   if (pl->mode == AMY_MODE_STORED) {
@@ -59,6 +61,17 @@ amy_status amy_batch_normalise(const amy_problem* p, Plan* pl) {
     q.variant = AMY_VARIANT_GROUP64;
     const amy_status st = amy_resolve(&q, 0, pl);
     if (st != AMY_OK) return st;
+  }
+  // The batched launch reserves its largest system's LDS for every
+  // workgroup: a LANES system with large per-lane tables would cut the
+  // residency of all of them, so it runs one wave per row instead (its
+  // state's tables take a few hundred bytes there)
+  if (D.variant == AMY_VARIANT_LANES && D.lds_bytes > BATCH_LANES_LDS) {
+    amy_problem q = *p;
+    q.mode = AMY_MODE_OTF;
+    q.variant = AMY_VARIANT_GROUP64;
+    Plan g;
+    if (amy_resolve(&q, 0, &g) == AMY_OK) *pl = g;
   }
   if (D.grp_g != 1 && D.grp_g != 64)
     return amy_fail(AMY_E_UNSUPPORTED, "batched launch: %d lanes per state", (int)D.grp_g);

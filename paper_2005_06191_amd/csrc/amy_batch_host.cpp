@@ -38,7 +38,7 @@ int amy_lds_blocks_per_cu(int dev, size_t lds) {
 // rows are walked 64 states per tile whatever the variant.
 static const int BATCH_LANES_LDS = 8 * 1024;  // bytes of per-lane tables a batched LANES system may take
 
-amy_status amy_batch_normalise(const amy_problem* p, Plan* pl) {
+amy_status amy_batch_normalise(const amy_problem* p, Plan* pl, int lanes_lds_cap) {
   DevProblem& D = pl->dev;
   if (pl->mode == AMY_MODE_STORED) {
     D.grp_g = 1;
@@ -62,11 +62,11 @@ amy_status amy_batch_normalise(const amy_problem* p, Plan* pl) {
     const amy_status st = amy_resolve(&q, 0, pl);
     if (st != AMY_OK) return st;
   }
-  // The batched launch reserves its largest system's LDS for every
-  // workgroup: a LANES system with large per-lane tables would cut the
-  // residency of all of them, so it runs one wave per row instead (its
+  // The persistent launch reserves its largest system's LDS for every
+  // workgroup: there a LANES system with large per-lane tables would cut
+  // the residency of all of them, so it runs one wave per row instead (its
   // state's tables take a few hundred bytes there)
-  if (D.variant == AMY_VARIANT_LANES && D.lds_bytes > BATCH_LANES_LDS) {
+  if (lanes_lds_cap > 0 && D.variant == AMY_VARIANT_LANES && D.lds_bytes > lanes_lds_cap) {
     amy_problem q = *p;
     q.mode = AMY_MODE_OTF;
     q.variant = AMY_VARIANT_GROUP64;
@@ -95,7 +95,7 @@ amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp
     if (q.variant == AMY_VARIANT_FIXED || q.variant == AMY_VARIANT_FACTORED || q.variant == AMY_VARIANT_INPUTS)
       q.variant = AMY_VARIANT_LANES;
     st = amy_resolve(&q, 0, &bp.plans[i]);
-    if (st == AMY_OK) st = amy_batch_normalise(&q, &bp.plans[i]);
+    if (st == AMY_OK) st = amy_batch_normalise(&q, &bp.plans[i], BATCH_LANES_LDS);
     if (st != AMY_OK) return amy_fail(st, "system %d: %s", i, amy_last_error());
     const DevProblem& D = bp.plans[i].dev;
     if (D.pd != 0 || D.noise != 0 || D.wrule != 0 || D.mult)

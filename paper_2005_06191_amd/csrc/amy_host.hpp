@@ -82,7 +82,10 @@ struct BatchTune {
 amy_status amy_batch_plan(const amy_problem* probs, int32_t count, BatchPlan& bp);
 // Workgroups of `lds` bytes of LDS resident on one CU of device dev.
 int amy_lds_blocks_per_cu(int dev, size_t lds);
-amy_status amy_batch_normalise(const amy_problem* p, Plan* pl);
+// lanes_lds_cap > 0: LANES systems whose per-lane tables exceed it run
+// GROUP64 instead (the persistent launch reserves its largest system's LDS
+// for every workgroup)
+amy_status amy_batch_normalise(const amy_problem* p, Plan* pl, int lanes_lds_cap = 0);
 amy_status amy_batch_run(const amy_problem* probs, const BatchPlan& bp, hipStream_t hs, char* ws,
                          double* const* V_out, int16_t* const* policy_out, bool want_tail, const BatchTune& tune,
                          float* ms_out);

@@ -1496,56 +1496,73 @@ __global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const
 
 // ------------------------------------- staged boxes, shared relative tables
 //
-// The unicycle's steps on the shared relative tables, with one workgroup
-// per (x, y) cell: lane t takes heading cell t (at most 64 cells).  Over
-// every heading and input, the x and y windows of that cell start within
-// 3 cells of each other (the drift is at most one cell), so the workgroup
-// copies the 7 x 7 rows of all headings that hold them from V into LDS once
-// per step (each row is contiguous in V) and every input contracts from
-// there.  The box starts at the smallest origin over its lanes and inputs,
-// clamped to the grid; a window outside it is gathered from V.  The order
-// of operations is that of k_sweep_rel, so the bits are the same.
-template <class SH>
+// The unicycle's steps on the shared relative tables, with one wave per
+// (x, y) cell: lane t takes heading cell t (at most 64 cells), and a
+// workgroup of CY waves takes CY cells adjacent in y.  Over every heading
+// and input, the x and y windows of a cell start within 3 cells of each
+// other (the drift is at most one cell), so the workgroup copies the
+// (L_x + 2) x (L_y + 1 + CY) rows of all headings that hold its windows from
+// V into LDS once per step (each row is contiguous in V; each wave copies a
+// share of the rows) and every input contracts from there.  The box starts
+// at the smallest origin over its lanes and inputs, clamped to the grid; a
+// window outside it is gathered from V.  The order of operations is that of
+// k_sweep_rel, so the bits are the same.  Two cells per workgroup share
+// their box's overlapping rows: 28 row loads per lane instead of 49, and 8
+// workgroups (16 waves) per CU where one cell each allowed 10 waves.
+template <class SH, int CY>
 struct RelBox {
   static_assert(SH::N == 3, "relative-table box: 3-D shapes");
-  static constexpr int C[3] = {SH::L[0] + 2, SH::L[1] + 2, 64};
+  static constexpr int C[3] = {SH::L[0] + 2, SH::L[1] + 1 + CY, 64};
   static constexpr int S[3] = {C[1] * 64, 64, 1};
   static constexpr int ROWS = C[0] * C[1];
   static constexpr int SIZE = ROWS * 64;
 };
 
-template <int KIND, class SH, int U, class MT, class AT, class VI, class VO, bool COMP>
-__global__ void __launch_bounds__(FIX_BLOCK) k_sweep_relbox(DevProblem P, const VI* __restrict__ Vin,
-                                                            VO* __restrict__ Vout, const uint8_t* __restrict__ label,
-                                                            int16_t* __restrict__ pol, const MT* __restrict__ rm,
-                                                            const int32_t* __restrict__ rlo) {
-  using BX = RelBox<SH>;
+// LDS of a relative-box workgroup: the box, then per wave its U partial
+// sums and dimension 0's masses ([slot][lane] each), then the shared fast
+// digit tables.
+template <class SH, int U, int CY, class MT, class AT, class VI>
+static size_t relbox_lds_bytes(int nf) {
+  return (size_t)RelBox<SH, CY>::SIZE * sizeof(VI) + (size_t)CY * U * 64 * sizeof(AT) +
+         (size_t)CY * SH::L[0] * 64 * sizeof(MT) + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) + (size_t)nf * 4;
+}
+
+template <int KIND, class SH, int U, class MT, class AT, class VI, class VO, bool COMP, int CY>
+__global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI* __restrict__ Vin,
+                                                          VO* __restrict__ Vout, const uint8_t* __restrict__ label,
+                                                          int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                          const int32_t* __restrict__ rlo) {
+  using BX = RelBox<SH, CY>;
   constexpr int N = 3;
   constexpr int F = N - 1;
   constexpr int LF = SH::L[F];
   static_assert(LF <= U && SH::LMAX <= REL_SLOTS, "relative-table sweep shape");
+  static_assert((BX::ROWS / CY) % 7 == 0 && BX::ROWS % CY == 0, "whole chunks of rows per wave");
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int wlo[2][CY];
   const int fd = P.m - 1, nf = P.ucount[fd], fm = P.rmult[F][fd];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   VI* box = reinterpret_cast<VI*>(smem);
   // the lane's U partial sums of one slow combination, read back by index
-  AT* asl = reinterpret_cast<AT*>(smem + BX::SIZE * sizeof(VI)) + threadIdx.x;
-  MT* t0 = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI) + (size_t)U * FIX_BLOCK * sizeof(AT)) + threadIdx.x;
-  MT* thm = reinterpret_cast<MT*>(smem + BX::SIZE * sizeof(VI) + (size_t)U * FIX_BLOCK * sizeof(AT)) +
-            SH::L[0] * FIX_BLOCK;
+  AT* asl = reinterpret_cast<AT*>(smem + BX::SIZE * sizeof(VI)) + w * U * 64 + lane;
+  unsigned char* after_asl = smem + BX::SIZE * sizeof(VI) + (size_t)CY * U * 64 * sizeof(AT);
+  MT* t0 = reinterpret_cast<MT*>(after_asl) + w * SH::L[0] * 64 + lane;
+  MT* thm = reinterpret_cast<MT*>(after_asl) + CY * SH::L[0] * 64;
   int32_t* thr = reinterpret_cast<int32_t*>(thm + nf * LF);
-  for (int f = threadIdx.x; f < nf; f += FIX_BLOCK) {
+  for (int f = (int)threadIdx.x; f < nf; f += 64 * CY) {
     const int e = P.rel_off[F] + f * fm;
 #pragma unroll
     for (int k = 0; k < LF; ++k) thm[f * LF + k] = rm[(int64_t)e * REL_SLOTS + k];
     thr[f] = rlo[e];
   }
-  const int lane = threadIdx.x;
   const int nF = P.count[F];
-  const uint32_t pair = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t nyb = (uint32_t)P.count[1] / (uint32_t)CY;
+  const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   int j[N];
-  j[1] = (int)(pair % (uint32_t)P.count[1]);
-  j[0] = (int)(pair / (uint32_t)P.count[1]);
+  j[1] = (int)(blk % nyb) * CY + w;
+  j[0] = (int)(blk / nyb);
   j[F] = lane;
+  const uint32_t pair = (uint32_t)j[0] * (uint32_t)P.count[1] + (uint32_t)j[1];
   const bool valid = lane < nF;
   const uint32_t s = pair * (uint32_t)nF + (uint32_t)lane;
   const uint8_t lb = valid ? label[s] : (uint8_t)LBL_ZERO;
@@ -1556,7 +1573,7 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_relbox(DevProblem P, const 
   }
   const int nslow = P.n_u / nf;
   // the box origin: the smallest x and y window origin over the free lanes
-  // and the slow digits (the fast digit moves only the heading)
+  // of every wave and the slow digits (the fast digit moves only the heading)
   int lo0 = P.count[0], lo1 = P.count[1];
   if (free) {
     InputWalk iw;
@@ -1580,31 +1597,45 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_relbox(DevProblem P, const 
     lo0 = min(lo0, __shfl_xor(lo0, off));
     lo1 = min(lo1, __shfl_xor(lo1, off));
   }
+  if constexpr (CY > 1) {
+    if (lane == 0) {
+      wlo[0][w] = lo0;
+      wlo[1][w] = lo1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CY; ++q) {
+      lo0 = min(lo0, wlo[0][q]);
+      lo1 = min(lo1, wlo[1][q]);
+    }
+  }
   const int b0 = __builtin_amdgcn_readfirstlane(min(lo0, P.count[0] - BX::C[0]));
   const int b1 = __builtin_amdgcn_readfirstlane(min(lo1, P.count[1] - BX::C[1]));
   const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
   {
-    // rows (x, y) of the box, each the run of all heading cells
+    // rows (x, y) of the box, each the run of all heading cells; wave w
+    // copies rows [w ROWS / CY, (w + 1) ROWS / CY)
     const uint32_t gl = ((uint32_t)b0 * (uint32_t)P.stride[0] + (uint32_t)b1 * (uint32_t)P.stride[1] +
                          (uint32_t)min(lane, nF - 1)) * (uint32_t)sizeof(VI);
-    constexpr int CH = 7;
-    static_assert(BX::ROWS % CH == 0, "whole chunks");
+    constexpr int CH = 7, PER = BX::ROWS / CY;
+    const int qw = w * PER;
 #pragma unroll
-    for (int q0 = 0; q0 < BX::ROWS; q0 += CH) {
+    for (int q0 = 0; q0 < PER; q0 += CH) {
       VI v[CH];
 #pragma unroll
       for (int q = 0; q < CH; ++q) {
-        const int rx = (q0 + q) / BX::C[1], ry = (q0 + q) % BX::C[1];
+        const int qq = qw + q0 + q;
+        const int rx = qq / BX::C[1], ry = qq % BX::C[1];
         v[q] = vb.load(gl, ((uint32_t)rx * (uint32_t)P.stride[0] + (uint32_t)ry * (uint32_t)P.stride[1]) *
                                (uint32_t)sizeof(VI));
       }
 #pragma unroll
-      for (int q = 0; q < CH; ++q) box[(q0 + q) * 64 + lane] = v[q];
+      for (int q = 0; q < CH; ++q) box[(qw + q0 + q) * 64 + lane] = v[q];
       __builtin_amdgcn_sched_barrier(0);
     }
   }
   __syncthreads();
-  if (!free) return;  // one wave per workgroup: no barrier follows
+  if (!free) return;  // no barrier follows
   const VLds<VI, BX> vl{box};
   int omin = nF;
   for (int f = 0; f < nf; ++f) omin = min(omin, min(max(j[F] + thr[f], 0), nF - LF));
@@ -1807,11 +1838,19 @@ struct FacLaunch {
         const size_t lds = (size_t)SH::L[0] * sizeof(MT) * FIX_BLOCK + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) +
                            (size_t)nf * 4;
         if constexpr (SH::N == 3) {
-          using BX = RelBox<SH>;
-          if (P.count[2] <= 64 && P.count[0] >= BX::C[0] && P.count[1] >= BX::C[1]) {
+          using B2 = RelBox<SH, 2>;
+          using B1 = RelBox<SH, 1>;
+          if (P.count[2] <= 64 && P.count[0] >= B2::C[0] && P.count[1] >= B2::C[1] && P.count[1] % 2 == 0) {
+            const dim3 gb((unsigned)(P.n_x / P.count[2] / 2)), b2(128);
+            const size_t lb = relbox_lds_bytes<SH, U, 2, MT, AT, VI>(nf);
+            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP, 2>), gb, b2, lb, st, P,
+                               (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
+            return;
+          }
+          if (P.count[2] <= 64 && P.count[0] >= B1::C[0] && P.count[1] >= B1::C[1]) {
             const dim3 gb((unsigned)(P.n_x / P.count[2]));
-            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP>), gb, b,
-                               lds + BX::SIZE * sizeof(VI) + (size_t)U * FIX_BLOCK * sizeof(AT), st, P,
+            const size_t lb = relbox_lds_bytes<SH, U, 1, MT, AT, VI>(nf);
+            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP, 1>), gb, b, lb, st, P,
                                (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
             return;
           }

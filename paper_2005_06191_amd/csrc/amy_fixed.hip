@@ -1506,9 +1506,10 @@ __global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const
 // share of the rows) and every input contracts from there.  The box starts
 // at the smallest origin over its lanes and inputs, clamped to the grid; a
 // window outside it is gathered from V.  The order of operations is that of
-// k_sweep_rel, so the bits are the same.  Two cells per workgroup share
-// their box's overlapping rows: 28 row loads per lane instead of 49, and 8
-// workgroups (16 waves) per CU where one cell each allowed 10 waves.
+// k_sweep_rel, so the bits are the same.  Cells of one workgroup share
+// their box's overlapping rows: with two, 28 row loads per lane instead of
+// 49, and 8 workgroups (16 waves) per CU where one cell each allowed 10
+// waves; with four, 18 row loads and 5 workgroups (20 waves) per CU.
 template <class SH, int CY>
 struct RelBox {
   static_assert(SH::N == 3, "relative-table box: 3-D shapes");
@@ -1537,7 +1538,6 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
   constexpr int F = N - 1;
   constexpr int LF = SH::L[F];
   static_assert(LF <= U && SH::LMAX <= REL_SLOTS, "relative-table sweep shape");
-  static_assert((BX::ROWS / CY) % 7 == 0 && BX::ROWS % CY == 0, "whole chunks of rows per wave");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int wlo[2][CY];
   const int fd = P.m - 1, nf = P.ucount[fd], fm = P.rmult[F][fd];
@@ -1614,23 +1614,25 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
   const VBuf<VI> vb(Vin, (uint32_t)P.n_x);
   {
     // rows (x, y) of the box, each the run of all heading cells; wave w
-    // copies rows [w ROWS / CY, (w + 1) ROWS / CY)
+    // copies rows [w PER, (w + 1) PER) that lie in the box, in chunks of 7
     const uint32_t gl = ((uint32_t)b0 * (uint32_t)P.stride[0] + (uint32_t)b1 * (uint32_t)P.stride[1] +
                          (uint32_t)min(lane, nF - 1)) * (uint32_t)sizeof(VI);
-    constexpr int CH = 7, PER = BX::ROWS / CY;
+    constexpr int CH = 7, PER = (BX::ROWS + CY - 1) / CY;
+    constexpr bool EXACT = PER * CY == BX::ROWS && PER % CH == 0;
     const int qw = w * PER;
 #pragma unroll
     for (int q0 = 0; q0 < PER; q0 += CH) {
       VI v[CH];
 #pragma unroll
       for (int q = 0; q < CH; ++q) {
-        const int qq = qw + q0 + q;
+        const int qq = EXACT ? qw + q0 + q : min(qw + q0 + q, BX::ROWS - 1);
         const int rx = qq / BX::C[1], ry = qq % BX::C[1];
         v[q] = vb.load(gl, ((uint32_t)rx * (uint32_t)P.stride[0] + (uint32_t)ry * (uint32_t)P.stride[1]) *
                                (uint32_t)sizeof(VI));
       }
 #pragma unroll
-      for (int q = 0; q < CH; ++q) box[(qw + q0 + q) * 64 + lane] = v[q];
+      for (int q = 0; q < CH; ++q)
+        if (EXACT || (q0 + q < PER && qw + q0 + q < BX::ROWS)) box[(qw + q0 + q) * 64 + lane] = v[q];
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -1838,8 +1840,16 @@ struct FacLaunch {
         const size_t lds = (size_t)SH::L[0] * sizeof(MT) * FIX_BLOCK + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) +
                            (size_t)nf * 4;
         if constexpr (SH::N == 3) {
+          using B4 = RelBox<SH, 4>;
           using B2 = RelBox<SH, 2>;
           using B1 = RelBox<SH, 1>;
+          if (P.count[2] <= 64 && P.count[0] >= B4::C[0] && P.count[1] >= B4::C[1] && P.count[1] % 4 == 0) {
+            const dim3 gb((unsigned)(P.n_x / P.count[2] / 4)), b4(256);
+            const size_t lb = relbox_lds_bytes<SH, U, 4, MT, AT, VI>(nf);
+            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP, 4>), gb, b4, lb, st, P,
+                               (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
+            return;
+          }
           if (P.count[2] <= 64 && P.count[0] >= B2::C[0] && P.count[1] >= B2::C[1] && P.count[1] % 2 == 0) {
             const dim3 gb((unsigned)(P.n_x / P.count[2] / 2)), b2(128);
             const size_t lb = relbox_lds_bytes<SH, U, 2, MT, AT, VI>(nf);

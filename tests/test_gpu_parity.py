@@ -34,11 +34,12 @@ def _uni_small(**kw):
                    name="unicycle-patch", **kw)
 
 
-def _uni_even(**kw):
-    # an even number of y cells: the relative-table steps take two cells per workgroup
+def _uni_even(ny=24, **kw):
+    # a number of y cells divisible by 4 (by 2 only, for ny=26): the
+    # relative-table steps take four (two) cells per workgroup
     p = W.unicycle3d(nxy=100, ntheta=60)
-    lo, h, cnt = W.tiling((0.0, 0.0, -math.pi), (2.2, 2.4, math.pi), (22, 24, 60))
-    return p.with_(lo=lo, h=h, count=cnt, target=W.box((1.5, 1.5), (2.2, 2.4), 3),
+    lo, h, cnt = W.tiling((0.0, 0.0, -math.pi), (2.2, 0.1 * ny, math.pi), (22, ny, 60))
+    return p.with_(lo=lo, h=h, count=cnt, target=W.box((1.5, 1.5), (2.2, 0.1 * ny), 3),
                    avoid=W.box((0.6, 0.6), (1.0, 1.2), 3), horizon=kw.pop("horizon", 8),
                    name="unicycle-even", **kw)
 
@@ -81,6 +82,7 @@ CASES = {
     "unicycle-patch-fast-fp32": lambda: _uni_small(precision="fp32", u_hi=(3.0, 1.0)),
     "unicycle-even-fp32": lambda: _uni_even(precision="fp32"),
     "unicycle-even-fast-fp32": lambda: _uni_even(precision="fp32", u_hi=(3.0, 1.0)),
+    "unicycle-y26-fp32": lambda: _uni_even(ny=26, precision="fp32"),
     "room-patch-fp32-otf": lambda: _room_small(precision="fp32"),
     "room-patch-fp64-otf": lambda: _room_small(precision="fp64"),
     "room-patch-fp64-stored": lambda: _room_small(precision="fp64", mode="stored"),
@@ -252,7 +254,8 @@ def test_fixed_shape_kernel_matches_generic(name):
 
 
 @pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "unicycle-patch-reach-fp32",
-                                  "unicycle-patch-fast-fp32", "unicycle-even-fp32", "unicycle-even-fast-fp32"])
+                                  "unicycle-patch-fast-fp32", "unicycle-even-fp32", "unicycle-even-fast-fp32",
+                                  "unicycle-y26-fp32"])
 def test_factored_sweep_matches_oracle_and_fixed(orc, name):
     """The factored sweep shares the outer contraction between inputs that
     differ only in the last digit: the window sum is re-associated, so it is

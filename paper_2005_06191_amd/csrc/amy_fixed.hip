@@ -1521,18 +1521,32 @@ struct RelBox {
 
 // LDS of a relative-box workgroup: the box, then per wave its U partial
 // sums and dimension 0's masses ([slot][lane] each), then the shared fast
-// digit tables.
+// digit tables; a first step that forms the row tails adds the heading's
+// FP64 memo entries of every fast digit ([digit][lane], 16-byte aligned).
 template <class SH, int U, int CY, class MT, class AT, class VI>
-static size_t relbox_lds_bytes(int nf) {
-  return (size_t)RelBox<SH, CY>::SIZE * sizeof(VI) + (size_t)CY * U * 64 * sizeof(AT) +
-         (size_t)CY * SH::L[0] * 64 * sizeof(MT) + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) + (size_t)nf * 4;
+static size_t relbox_lds_bytes(int nf, bool tail) {
+  const size_t b = (size_t)RelBox<SH, CY>::SIZE * sizeof(VI) + (size_t)CY * U * 64 * sizeof(AT) +
+                   (size_t)CY * SH::L[0] * 64 * sizeof(MT) + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) + (size_t)nf * 4;
+  return tail ? ((b + 15) & ~(size_t)15) + (size_t)nf * 64 * 16 : b;
 }
 
-template <int KIND, class SH, int U, class MT, class AT, class VI, class VO, bool COMP, int CY>
+// Where a first step on the relative box finds the memoised FP64 kept-window
+// and grid masses that k_tail_memo reads (the same entries, numbered the
+// same way): entry off[i] + cx * rc[i] + c of dimension i, with context cell
+// cx = sum_k j[ctx[i][k]] mult[i][k].  The last dimension's context is its
+// own cell alone, so every wave of a workgroup (the same heading cells on
+// its lanes) shares those entries.
+struct MemoTail {
+  const double2* wg;
+  int32_t off[3], rc[3], cn[3], ctx[3][4], mult[3][4];
+};
+
+template <int KIND, class SH, int U, class MT, class AT, class VI, class VO, bool COMP, int CY, bool TAIL>
 __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI* __restrict__ Vin,
                                                           VO* __restrict__ Vout, const uint8_t* __restrict__ label,
                                                           int16_t* __restrict__ pol, const MT* __restrict__ rm,
-                                                          const int32_t* __restrict__ rlo) {
+                                                          const int32_t* __restrict__ rlo, MemoTail mt,
+                                                          unsigned long long* __restrict__ tailmax) {
   using BX = RelBox<SH, CY>;
   constexpr int N = 3;
   constexpr int F = N - 1;
@@ -1556,6 +1570,12 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
     thr[f] = rlo[e];
   }
   const int nF = P.count[F];
+  double2* fent = reinterpret_cast<double2*>(
+      (reinterpret_cast<uintptr_t>(thr + nf) + 15) & ~(uintptr_t)15);  // [fast digit][lane]
+  if constexpr (TAIL) {
+    const int64_t fb = mt.off[F] + (int64_t)min(lane, nF - 1) * mt.mult[F][0] * mt.rc[F];
+    for (int f = w; f < nf; f += CY) fent[f * 64 + lane] = mt.wg[fb + (int64_t)f * fm];
+  }
   const uint32_t nyb = (uint32_t)P.count[1] / (uint32_t)CY;
   const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
   int j[N];
@@ -1637,8 +1657,25 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
     }
   }
   __syncthreads();
-  if (!free) return;  // no barrier follows
+  double tmax = 0.0;
+  do {
+  if (!free) break;  // no barrier follows
   const VLds<VI, BX> vl{box};
+  // the row tails' context entries of dimensions 0 and 1
+  int64_t tb[2] = {0, 0};
+  if constexpr (TAIL) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int64_t cx = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < mt.cn[i]) {
+          const int d = mt.ctx[i][k];
+          cx += (int64_t)(d == 0 ? j[0] : d == 1 ? j[1] : j[2]) * mt.mult[i][k];
+        }
+      tb[i] = mt.off[i] + cx * mt.rc[i];
+    }
+  }
   int omin = nF;
   for (int f = 0; f < nf; ++f) omin = min(omin, min(max(j[F] + thr[f], 0), nF - LF));
   FixedRow<SH, MT> R;
@@ -1649,6 +1686,20 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
   for (int sc = 0; sc < nslow; ++sc) {
     uint32_t base = (uint32_t)omin;
     int r[N];
+    double2 ex, ey;
+    if constexpr (TAIL) {
+      // this slow combination's entries of dimensions 0 and 1, loaded now
+      // and used after the contraction
+      int64_t e0 = tb[0], e1 = tb[1];
+#pragma unroll
+      for (int k = 0; k < AMY_MAXI; ++k)
+        if (k < fd) {
+          e0 += (int64_t)iw.dig[k] * P.rmult[0][k];
+          e1 += (int64_t)iw.dig[k] * P.rmult[1][k];
+        }
+      ex = mt.wg[e0];
+      ey = mt.wg[e1];
+    }
     rel_load<0, SH, MT>(P, iw, j, rm, rlo, R, r);
     rel_place<0, SH, MT>(P, r, t0, R, base);
     const int o0 = min(max(r[0], 0), P.count[0] - SH::L[0]) - b0;
@@ -1661,6 +1712,15 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
       contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
 #pragma unroll
     for (int t = 0; t < U; ++t) asl[t * FIX_BLOCK] = A[t];
+    if constexpr (TAIL) {
+      // the row's kept-window and grid masses, multiplied in dimension
+      // order as k_tail_memo does, so the max is the same bits
+      const double w01 = ex.x * ey.x, g01 = ex.y * ey.y;
+      for (int f = 0; f < nf; ++f) {
+        const double2 ef = fent[f * 64 + lane];
+        tmax = fmax(tmax, g01 * ef.y - w01 * ef.x);
+      }
+    }
     for (int f = 0; f < nf; ++f, ++u) {
       const int g = j[F] + thr[f] - omin;  // A index of the first kept cell
       AT q = AT(0);
@@ -1687,6 +1747,8 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
   }
   Vout[s] = VO(best);
   if (pol) pol[s] = (int16_t)arg;
+  } while (false);
+  if constexpr (TAIL) wave_max_to(tmax, tailmax);
 }
 
 // ------------------------------------------------------------- launchers
@@ -1823,48 +1885,81 @@ struct FacLaunch {
   // Window origins move by at most ceil(drift range / h) cells over the fast
   // digit, plus one for rounding at a cell boundary; the union adds L_F.
   static int span_bound(const DevProblem& P);
+  // Cells per relative-box workgroup (4, 2 or 1 adjacent in y, as the y
+  // count allows), 0 when the box does not fit the grid.
+  static int relbox_cy(const DevProblem& P) {
+    if constexpr (SH::N == 3 && RelDrift<KIND, SH::N>::ok) {
+      if (P.rel_entries <= 0 || P.count[2] > 64) return 0;
+      if (P.count[0] >= RelBox<SH, 4>::C[0] && P.count[1] >= RelBox<SH, 4>::C[1] && P.count[1] % 4 == 0) return 4;
+      if (P.count[0] >= RelBox<SH, 2>::C[0] && P.count[1] >= RelBox<SH, 2>::C[1] && P.count[1] % 2 == 0) return 2;
+      if (P.count[0] >= RelBox<SH, 1>::C[0] && P.count[1] >= RelBox<SH, 1>::C[1]) return 1;
+    }
+    return 0;
+  }
+  // Cells per relative-box workgroup of a first step that forms the row
+  // tails with these element types: the most (4, 2 or 1) whose LDS stays
+  // within 64 KB, 0 when none does.
+  template <class MT, class AT, class VI>
+  static int tail_cy(const DevProblem& P) {
+    const int nf = P.ucount[P.m - 1];
+    for (int cy = relbox_cy(P); cy >= 1; cy /= 2) {
+      const size_t lb = cy == 4   ? relbox_lds_bytes<SH, U, 4, MT, AT, VI>(nf, true)
+                        : cy == 2 ? relbox_lds_bytes<SH, U, 2, MT, AT, VI>(nf, true)
+                                  : relbox_lds_bytes<SH, U, 1, MT, AT, VI>(nf, true);
+      if (lb <= 64 * 1024) return cy;
+    }
+    return 0;
+  }
+  // The relative-box sweep can form the first step's row tails from the
+  // memoised tables of T: the last dimension's context is its own cell
+  // alone and some box of the plan's sweeps fits the LDS.
+  static bool fuses_tail(const DevProblem& P, const DevProblem& T, bool f64) {
+    const int F = SH::N - 1;
+    if (T.tables != 2 || T.mctx_n[F] != 1 || T.mctx[F][0] != F) return false;
+    for (int i = 0; i < F; ++i)
+      if (T.mctx_n[i] < 1 || T.mctx_n[i] > 4) return false;
+    if (f64) return tail_cy<double, double, double>(P) > 0;
+    return tail_cy<float, float, float>(P) > 0 && tail_cy<float, double, float>(P) > 0;
+  }
+  template <class MT, class AT, class VI, class VO, bool COMP, int CY, bool TAIL>
+  static void relbox(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                     const MT* rm, const int32_t* ro, const MemoTail& mt, unsigned long long* tailmax,
+                     hipStream_t st) {
+    const dim3 gb((unsigned)(P.n_x / P.count[2] / CY)), bb(64 * CY);
+    const size_t lb = relbox_lds_bytes<SH, U, CY, MT, AT, VI>(P.ucount[P.m - 1], TAIL);
+    hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP, CY, TAIL>), gb, bb, lb, st, P,
+                       (const VI*)Vin, (VO*)Vout, label, pol, rm, ro, mt, tailmax);
+  }
+  // mt: the memoised tables for the row tails (with tailmax, when
+  // fuses_tail holds), else nullptr
   template <class MT, class AT, class VI, class VO, bool COMP>
   static void go(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
-                 unsigned long long* tailmax, const void* rel, hipStream_t st) {
+                 unsigned long long* tailmax, const void* rel, hipStream_t st, const MemoTail* mt) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
     if constexpr (RelDrift<KIND, SH::N>::ok) {
       if (rel && P.rel_entries > 0) {
-        if (tailmax) {  // the first step: its row tails in a pass of their own
+        const bool fuse = tailmax && mt && tail_cy<MT, AT, VI>(P) > 0;
+        const int cy = fuse ? tail_cy<MT, AT, VI>(P) : relbox_cy(P);
+        if (tailmax && !fuse) {  // the first step: its row tails in a pass of their own
           const size_t tl = (size_t)(P.lds_bytes_tail - P.lds_tail_off);
           hipLaunchKernelGGL((k_tail_cached<KIND, SH::N>), g, b, tl, st, P, label, tailmax);
         }
         const MT* rm = (const MT*)rel;
         const int32_t* ro = (const int32_t*)((const char*)rel +
                                              (((uint64_t)P.rel_entries * REL_SLOTS * sizeof(MT) + 255) & ~255ull));
+        const MemoTail m0 = fuse ? *mt : MemoTail{};
+        switch (fuse ? -cy : cy) {
+          case 4: relbox<MT, AT, VI, VO, COMP, 4, false>(P, Vin, Vout, label, pol, rm, ro, m0, nullptr, st); return;
+          case 2: relbox<MT, AT, VI, VO, COMP, 2, false>(P, Vin, Vout, label, pol, rm, ro, m0, nullptr, st); return;
+          case 1: relbox<MT, AT, VI, VO, COMP, 1, false>(P, Vin, Vout, label, pol, rm, ro, m0, nullptr, st); return;
+          case -4: relbox<MT, AT, VI, VO, COMP, 4, true>(P, Vin, Vout, label, pol, rm, ro, m0, tailmax, st); return;
+          case -2: relbox<MT, AT, VI, VO, COMP, 2, true>(P, Vin, Vout, label, pol, rm, ro, m0, tailmax, st); return;
+          case -1: relbox<MT, AT, VI, VO, COMP, 1, true>(P, Vin, Vout, label, pol, rm, ro, m0, tailmax, st); return;
+          default: break;
+        }
         const int nf = P.ucount[P.m - 1];
         const size_t lds = (size_t)SH::L[0] * sizeof(MT) * FIX_BLOCK + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) +
                            (size_t)nf * 4;
-        if constexpr (SH::N == 3) {
-          using B4 = RelBox<SH, 4>;
-          using B2 = RelBox<SH, 2>;
-          using B1 = RelBox<SH, 1>;
-          if (P.count[2] <= 64 && P.count[0] >= B4::C[0] && P.count[1] >= B4::C[1] && P.count[1] % 4 == 0) {
-            const dim3 gb((unsigned)(P.n_x / P.count[2] / 4)), b4(256);
-            const size_t lb = relbox_lds_bytes<SH, U, 4, MT, AT, VI>(nf);
-            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP, 4>), gb, b4, lb, st, P,
-                               (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
-            return;
-          }
-          if (P.count[2] <= 64 && P.count[0] >= B2::C[0] && P.count[1] >= B2::C[1] && P.count[1] % 2 == 0) {
-            const dim3 gb((unsigned)(P.n_x / P.count[2] / 2)), b2(128);
-            const size_t lb = relbox_lds_bytes<SH, U, 2, MT, AT, VI>(nf);
-            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP, 2>), gb, b2, lb, st, P,
-                               (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
-            return;
-          }
-          if (P.count[2] <= 64 && P.count[0] >= B1::C[0] && P.count[1] >= B1::C[1]) {
-            const dim3 gb((unsigned)(P.n_x / P.count[2]));
-            const size_t lb = relbox_lds_bytes<SH, U, 1, MT, AT, VI>(nf);
-            hipLaunchKernelGGL((k_sweep_relbox<KIND, SH, U, MT, AT, VI, VO, COMP, 1>), gb, b, lb, st, P,
-                               (const VI*)Vin, (VO*)Vout, label, pol, rm, ro);
-            return;
-          }
-        }
         hipLaunchKernelGGL((k_sweep_rel<KIND, SH, U, MT, AT, VI, VO, COMP>), g, b, lds, st, P, (const VI*)Vin,
                            (VO*)Vout, label, pol, rm, ro);
         return;
@@ -1881,12 +1976,13 @@ struct FacLaunch {
                          (const VI*)Vin, (VO*)Vout, label, pol, tailmax, t0);
   }
   static hipError_t sweep(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout, const uint8_t* label,
-                          int16_t* pol, unsigned long long* tailmax, const void* rel, hipStream_t st) {
+                          int16_t* pol, unsigned long long* tailmax, const void* rel, hipStream_t st,
+                          const MemoTail* mt) {
     switch (sk) {
-      case SWEEP_F64: go<double, double, double, double, false>(P, Vin, Vout, label, pol, tailmax, rel, st); break;
-      case SWEEP_F32: go<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, rel, st); break;
+      case SWEEP_F64: go<double, double, double, double, false>(P, Vin, Vout, label, pol, tailmax, rel, st, mt); break;
+      case SWEEP_F32: go<float, float, float, float, true>(P, Vin, Vout, label, pol, tailmax, rel, st, mt); break;
       case SWEEP_F32_LAST:
-        go<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, rel, st);
+        go<float, double, float, double, false>(P, Vin, Vout, label, pol, tailmax, rel, st, mt);
         break;
     }
     return hipGetLastError();
@@ -1958,12 +2054,38 @@ bool amy_fac_available(const DevProblem& P) {
   return false;
 }
 
+bool amy_fac_fuses_tail(const DevProblem& P, const DevProblem& T, bool f64) {
+#define X(K, SH, U) \
+  if (FacLaunch<K, SH, U>::feasible(P)) return FacLaunch<K, SH, U>::fuses_tail(P, T, f64);
+  AMY_FAC_SHAPES(X)
+#undef X
+  return false;
+}
+
 hipError_t amy_launch_sweep_fac(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
                                 const uint8_t* label, int16_t* pol, unsigned long long* tailmax, const void* rel,
-                                hipStream_t st) {
+                                hipStream_t st, const DevProblem* tail_dev, const void* tail_tab) {
+  MemoTail mt{};
+  const bool fused = tailmax && tail_dev && tail_tab;
+  if (fused) {
+    const bool f64 = (sk == SWEEP_F64);
+    if (!amy_fac_fuses_tail(P, *tail_dev, f64)) return hipErrorInvalidValue;
+    int lmax = 1;
+    for (int i = 0; i < tail_dev->n; ++i) lmax = tail_dev->L[i] > lmax ? tail_dev->L[i] : lmax;
+    mt.wg = (const double2*)((const char*)tail_tab + memo_wg_offset(*tail_dev, amy_memo_rec(lmax), f64 ? 8 : 4));
+    for (int i = 0; i < 3; ++i) {
+      mt.off[i] = tail_dev->rel_off[i];
+      mt.rc[i] = tail_dev->rcount[i];
+      mt.cn[i] = tail_dev->mctx_n[i];
+      for (int k = 0; k < 4; ++k) {
+        mt.ctx[i][k] = tail_dev->mctx[i][k];
+        mt.mult[i][k] = tail_dev->mmult[i][k];
+      }
+    }
+  }
 #define X(K, SH, U)                            \
   if (FacLaunch<K, SH, U>::feasible(P)) \
-    return FacLaunch<K, SH, U>::sweep(P, sk, Vin, Vout, label, pol, tailmax, rel, st);
+    return FacLaunch<K, SH, U>::sweep(P, sk, Vin, Vout, label, pol, tailmax, rel, st, fused ? &mt : nullptr);
   AMY_FAC_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

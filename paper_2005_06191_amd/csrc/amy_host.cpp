@@ -748,7 +748,7 @@ extern "C" amy_status amy_query(const amy_problem* p, uint64_t ws_budget, amy_in
 // labels and V_{T_d+1} (and stored rows) are in place: reads V buffer
 // (T_d - k) & 1 and writes the other one, or V_out at k = 1.
 hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
-                            int k, bool want_tail) {
+                            int k, bool want_tail, bool tail_memo) {
   const DevProblem& D = pl.dev;
   char* base = (char*)ws;
   const uint8_t* label = (const uint8_t*)(base + pl.off_label);
@@ -763,9 +763,11 @@ hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_
   if (pl.mode == AMY_MODE_STORED)
     return amy_launch_sweep_stored(D, sk, base + pl.off_T, (const int32_t*)(base + pl.off_org), Vb[cur], out,
                                    label, pk, st);
-  if (D.variant == AMY_VARIANT_FACTORED)
+  if (D.variant == AMY_VARIANT_FACTORED) {
+    const bool fused = tail && tail_memo;
     return amy_launch_sweep_fac(D, sk, Vb[cur], out, label, pk, tail, D.rel_entries > 0 ? base + pl.off_rel : nullptr,
-                                st);
+                                st, fused ? &pl.tail_dev : nullptr, fused ? base + pl.off_tailtab : nullptr);
+  }
   if (D.variant == AMY_VARIANT_FIXED)
     return amy_launch_sweep_fixed(D, sk, Vb[cur], out, label, pk, tail, D.rel_entries > 0 ? base + pl.off_rel : nullptr,
                                   st);
@@ -805,18 +807,21 @@ amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, 
                               want_tail ? tailmax : nullptr, st)) != hipSuccess)
       return amy_hip_fail(e, "build kernel");
   }
-  // the factored first step's tails from memoised tables, built here
+  // the factored first step's tails from memoised tables, built here: inside
+  // the first sweep where it can take them, else in a pass of their own
   const bool tail_tab = want_tail && horizon > 0 && !stored && pl.tail_memo;
+  const bool tail_fused = tail_tab && !pl.user && amy_fac_fuses_tail(D, pl.tail_dev, pl.f64);
   if (tail_tab) {
     void* tab = base + pl.off_tailtab;
     if ((e = amy_launch_memo_build(pl.tail_dev, pl.f64, tab, st)) != hipSuccess ||
-        (e = amy_launch_tail_memo(pl.tail_dev, pl.f64, label, tab, tailmax, st)) != hipSuccess)
+        (!tail_fused && (e = amy_launch_tail_memo(pl.tail_dev, pl.f64, label, tab, tailmax, st)) != hipSuccess))
       return amy_hip_fail(e, "tail tables");
   }
   if (tm) hipEventRecord(tm->ev[1], st);
   for (int k = horizon; k >= 1; --k) {
     if (tm && k == 1) hipEventRecord(tm->ev[2], st);
-    if ((e = amy_enqueue_step(pl, st, ws, V_out, pol, horizon, k, want_tail && !tail_tab)) != hipSuccess)
+    if ((e = amy_enqueue_step(pl, st, ws, V_out, pol, horizon, k, want_tail && (!tail_tab || tail_fused),
+                              tail_fused)) != hipSuccess)
       return amy_hip_fail(e, "sweep kernel");
     if (tm && k == horizon) hipEventRecord(tm->ev[5], st);
   }

@@ -49,8 +49,10 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl);
 amy_status amy_enqueue(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
                        bool want_tail, Timing* tm);
 hipError_t amy_enqueue_prepare(const Plan& pl, hipStream_t st, void* ws, int horizon);
+// tail_memo: the first step forms the row tails inside the factored sweep
+// from the memoised tables (built, amy_fac_fuses_tail true for the plan)
 hipError_t amy_enqueue_step(const Plan& pl, hipStream_t st, void* ws, double* V_out, int16_t* pol, int horizon,
-                            int k, bool want_tail);
+                            int k, bool want_tail, bool tail_memo = false);
 
 #include <string>
 #include <vector>

@@ -50,11 +50,16 @@ size_t amy_tail_memo_lds(const DevProblem& P);
 hipError_t amy_launch_tail_memo(const DevProblem& P, bool f64, const uint8_t* label, const void* tables,
                                 unsigned long long* tailmax, hipStream_t st);
 // Factored compiled-shape sweep (inputs sharing the outer dimensions' windows).
-// rel: the shared relative tables (when P.rel_entries > 0) for the steps
-// without the FP64 tail; the tail step builds its tables per state.
+// rel: the shared relative tables (when P.rel_entries > 0).  A step given
+// tailmax forms the FP64 row tails: from the memoised tables (tail_dev, the
+// plan of amy_launch_tail_memo, and tail_tab, built by amy_launch_memo_build
+// with it) inside the sweep when amy_fac_fuses_tail says so, else in a pass
+// of its own that builds the tables per state.
 bool amy_fac_available(const DevProblem& P);
 int amy_rel_plan(DevProblem& P);
 hipError_t amy_launch_rel_build(const DevProblem& P, bool f64, void* rel, hipStream_t st);
+bool amy_fac_fuses_tail(const DevProblem& P, const DevProblem& tail_dev, bool f64);
 hipError_t amy_launch_sweep_fac(const DevProblem& P, SweepKind sk, const void* Vin, void* Vout,
                                 const uint8_t* label, int16_t* pol, unsigned long long* tailmax, const void* rel,
-                                hipStream_t st);
+                                hipStream_t st, const DevProblem* tail_dev = nullptr,
+                                const void* tail_tab = nullptr);

@@ -100,6 +100,24 @@ def contraction_flops_per_row(plan) -> float:
     return f
 
 
+def factored_flops_per_row(plan, n_fast) -> float:
+    """The factored sweep's contraction per row: for each state and
+    combination of the slow inputs, the outer dimensions' windows are
+    contracted once for the U innermost cells that the fast input's windows
+    can reach (2 (U W' + U W'/L_{n-2} + ... + U L_0) flops with
+    W' = L_0 ... L_{n-2}, dimension by dimension), and each of the n_fast
+    inputs then sums its own L_{n-1} of those U partial sums (2 L_{n-1}
+    flops).  U = L_{n-1} + 3 for the compiled shapes (a fast-digit drift of
+    at most two cells, plus one for rounding)."""
+    L = [x for x in plan["window"] if x > 0]
+    U = L[-1] + 3
+    outer, w = 0.0, float(U * math.prod(L[:-1]))
+    for l in reversed(L[:-1]):
+        outer += 2.0 * w
+        w /= l
+    return outer / n_fast + 2.0 * L[-1]
+
+
 def row_equivalent_flops_per_row(plan) -> float:
     """3W + C_erfc * edges: the per-row count of a sweep that builds every
     row's 1-D tables itself and multiplies each cell's mass out (a
@@ -421,15 +439,19 @@ def bench_solve(workload, mode, variant, steps, warmup, fp64=True, check=True):
     sweep_ms = statistics.mean(r32["main"]) / n_main
     prof = _profiled(workload, mode, plan["variant"])
     if mode == "otf":
-        fl = contraction_flops_per_row(plan)
+        factored = plan["variant"] == "factored"
+        fl = factored_flops_per_row(plan, p32.u_count[-1]) if factored else contraction_flops_per_row(plan)
         achieved = fl * rows / (sweep_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic_for(workload, mode, plan["variant"]),
                 "kernel": f"sweep {plan['variant']} (FP32)", "kernel_avg_ms": round(sweep_ms, 4),
                 "launches_timed": n_main * steps, "flops_per_row": fl, "rows_per_launch": rows,
-                "work": "per-row window contraction done dimension by dimension, "
-                        "2 (W + W/L_n + ... + L_1) flops; the 1-D tables are built once per solve",
+                "work": ("factored contraction: the outer windows once per state and slow-input "
+                         "combination for the U cells the fast input reaches, 2 L_0 U (L_1 + 1) / n_fast "
+                         "+ 2 L_2 flops per row" if factored else
+                         "per-row window contraction done dimension by dimension, "
+                         "2 (W + W/L_n + ... + L_1) flops; the 1-D tables are built once per solve"),
                 "peak_without_packed_fp32": PEAK_FP64_TFLOPS,
                 "frac_without_packed_fp32": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "row_equivalent": {"flops_per_row": row_equivalent_flops_per_row(plan),

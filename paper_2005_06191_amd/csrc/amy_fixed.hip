@@ -659,10 +659,15 @@ __global__ void __launch_bounds__(64) k_rel_build(DevProblem P, MT* __restrict__
   const int cx = P.rctx[i];
   const double xc = cx >= 0 ? P.lo[cx] + ((double)j + 0.5) * P.h[cx] : 0.0;
   const double dr = RelDrift<KIND, N>::drift(P, i, xc, u);
-  // kept cells r (relative to the state's cell): |r h - drift| <= x*
+  // kept cells r (relative to the state's cell): the centre rule keeps
+  // |r h - drift| <= x*; the intersect rule keeps every cell meeting
+  // [drift - x*, drift + x*], i.e. (r - 1/2) h < drift + x* and
+  // (r + 1/2) h > drift - x*
   const int L = P.L[i];
-  const int r0 = (int)ceil((dr - P.xstar[i]) * P.inv_h[i]);
-  int r1 = (int)floor((dr + P.xstar[i]) * P.inv_h[i]);
+  const bool inter = P.wrule == 1;
+  const int r0 = inter ? (int)floor((dr - P.xstar[i]) * P.inv_h[i] + 0.5)
+                       : (int)ceil((dr - P.xstar[i]) * P.inv_h[i]);
+  int r1 = inter ? (int)ceil((dr + P.xstar[i]) * P.inv_h[i] + 0.5) - 1 : (int)floor((dr + P.xstar[i]) * P.inv_h[i]);
   r1 = min(r1, r0 + L - 1);
   const int cnt = max(0, r1 - r0 + 1);
   // edge below relative cell r: z = ((r - 1/2) h - drift) / sigma
@@ -1885,28 +1890,24 @@ struct FacLaunch {
   // Window origins move by at most ceil(drift range / h) cells over the fast
   // digit, plus one for rounding at a cell boundary; the union adds L_F.
   static int span_bound(const DevProblem& P);
-  // Cells per relative-box workgroup (4, 2 or 1 adjacent in y, as the y
-  // count allows), 0 when the box does not fit the grid.
-  static int relbox_cy(const DevProblem& P) {
+  // Cells per relative-box workgroup with these element types: the most
+  // (4, 2 or 1 adjacent in y) that the y count divides, whose box fits the
+  // grid and whose LDS (with the tail's entries when tail) stays within
+  // 64 KB; 0 when none does.
+  template <class MT, class AT, class VI>
+  static int relbox_cy(const DevProblem& P, bool tail) {
     if constexpr (SH::N == 3 && RelDrift<KIND, SH::N>::ok) {
       if (P.rel_entries <= 0 || P.count[2] > 64) return 0;
-      if (P.count[0] >= RelBox<SH, 4>::C[0] && P.count[1] >= RelBox<SH, 4>::C[1] && P.count[1] % 4 == 0) return 4;
-      if (P.count[0] >= RelBox<SH, 2>::C[0] && P.count[1] >= RelBox<SH, 2>::C[1] && P.count[1] % 2 == 0) return 2;
-      if (P.count[0] >= RelBox<SH, 1>::C[0] && P.count[1] >= RelBox<SH, 1>::C[1]) return 1;
-    }
-    return 0;
-  }
-  // Cells per relative-box workgroup of a first step that forms the row
-  // tails with these element types: the most (4, 2 or 1) whose LDS stays
-  // within 64 KB, 0 when none does.
-  template <class MT, class AT, class VI>
-  static int tail_cy(const DevProblem& P) {
-    const int nf = P.ucount[P.m - 1];
-    for (int cy = relbox_cy(P); cy >= 1; cy /= 2) {
-      const size_t lb = cy == 4   ? relbox_lds_bytes<SH, U, 4, MT, AT, VI>(nf, true)
-                        : cy == 2 ? relbox_lds_bytes<SH, U, 2, MT, AT, VI>(nf, true)
-                                  : relbox_lds_bytes<SH, U, 1, MT, AT, VI>(nf, true);
-      if (lb <= 64 * 1024) return cy;
+      const int nf = P.ucount[P.m - 1];
+      if (P.count[0] >= RelBox<SH, 4>::C[0] && P.count[1] >= RelBox<SH, 4>::C[1] && P.count[1] % 4 == 0 &&
+          relbox_lds_bytes<SH, U, 4, MT, AT, VI>(nf, tail) <= 64 * 1024)
+        return 4;
+      if (P.count[0] >= RelBox<SH, 2>::C[0] && P.count[1] >= RelBox<SH, 2>::C[1] && P.count[1] % 2 == 0 &&
+          relbox_lds_bytes<SH, U, 2, MT, AT, VI>(nf, tail) <= 64 * 1024)
+        return 2;
+      if (P.count[0] >= RelBox<SH, 1>::C[0] && P.count[1] >= RelBox<SH, 1>::C[1] &&
+          relbox_lds_bytes<SH, U, 1, MT, AT, VI>(nf, tail) <= 64 * 1024)
+        return 1;
     }
     return 0;
   }
@@ -1918,8 +1919,8 @@ struct FacLaunch {
     if (T.tables != 2 || T.mctx_n[F] != 1 || T.mctx[F][0] != F) return false;
     for (int i = 0; i < F; ++i)
       if (T.mctx_n[i] < 1 || T.mctx_n[i] > 4) return false;
-    if (f64) return tail_cy<double, double, double>(P) > 0;
-    return tail_cy<float, float, float>(P) > 0 && tail_cy<float, double, float>(P) > 0;
+    if (f64) return relbox_cy<double, double, double>(P, true) > 0;
+    return relbox_cy<float, float, float>(P, true) > 0 && relbox_cy<float, double, float>(P, true) > 0;
   }
   template <class MT, class AT, class VI, class VO, bool COMP, int CY, bool TAIL>
   static void relbox(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
@@ -1938,8 +1939,8 @@ struct FacLaunch {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
     if constexpr (RelDrift<KIND, SH::N>::ok) {
       if (rel && P.rel_entries > 0) {
-        const bool fuse = tailmax && mt && tail_cy<MT, AT, VI>(P) > 0;
-        const int cy = fuse ? tail_cy<MT, AT, VI>(P) : relbox_cy(P);
+        const bool fuse = tailmax && mt && relbox_cy<MT, AT, VI>(P, true) > 0;
+        const int cy = relbox_cy<MT, AT, VI>(P, fuse);
         if (tailmax && !fuse) {  // the first step: its row tails in a pass of their own
           const size_t tl = (size_t)(P.lds_bytes_tail - P.lds_tail_off);
           hipLaunchKernelGGL((k_tail_cached<KIND, SH::N>), g, b, tl, st, P, label, tailmax);
@@ -2035,14 +2036,22 @@ using ShapeLinear2 = ShapeT<28, 28, 28>;
   X(AMY_DYN_AFFINE_, ShapeLinear2)
 
 // Unicycle: the heading moves by tau * omega, omega the last input.
-template <>
-int FacLaunch<AMY_DYN_UNICYCLE_, ShapeUnicycle, 5>::span_bound(const DevProblem& P) {
+static int unicycle_span(const DevProblem& P) {
   const int F = 2, fd = P.m - 1;
   const double range = fabs(P.params[0]) * (P.uhi[fd] - P.ulo[fd]);
   return (int)ceil(range * P.inv_h[F] - 1e-12) + 1 + P.L[F];
 }
+template <>
+int FacLaunch<AMY_DYN_UNICYCLE_, ShapeUnicycle, 5>::span_bound(const DevProblem& P) {
+  return unicycle_span(P);
+}
+template <>
+int FacLaunch<AMY_DYN_UNICYCLE_, ShapeUnicycleWide, 6>::span_bound(const DevProblem& P) {
+  return unicycle_span(P);
+}
 
-#define AMY_FAC_SHAPES(X) X(AMY_DYN_UNICYCLE_, ShapeUnicycle, 5)
+// (the centre rule's 5 x 5 x 2 windows; the intersect rule's 6 x 6 x 3)
+#define AMY_FAC_SHAPES(X) X(AMY_DYN_UNICYCLE_, ShapeUnicycle, 5) X(AMY_DYN_UNICYCLE_, ShapeUnicycleWide, 6)
 
 bool amy_fac_available(const DevProblem& P) {
   const uint64_t vbytes = (uint64_t)P.n_x * 8u;

@@ -595,13 +595,9 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
   // variants that fit: one lane per state needs every lane's 1-D tables in
   // LDS; the group variants need one set per state of the block
   const bool lanes_ok = (plan_tables(p, pl) == AMY_OK);
-  // the compiled-shape sweeps build normal masses with the centre rule for
-  // rows without a disturbance; everything else runs the run-time-window ones
-  const bool plain = pl->dev.pd == 0 && pl->dev.noise == AMY_NOISE_NORMAL && pl->dev.wrule == AMY_WINDOW_CENTRE &&
-                     !pl->dev.mult;
-  // the compiled shapes' own tables are additive normal masses over the
-  // window either rule gives; only the factored sweep's shared relative
-  // tables assume the centre rule
+  // the compiled shapes' own tables, and the factored sweep's shared
+  // relative tables, are additive normal masses over the window either rule
+  // gives, for rows without a disturbance
   const bool normal_masses = pl->dev.pd == 0 && pl->dev.noise == AMY_NOISE_NORMAL && !pl->dev.mult;
   // the other noise models and the intersect window (additive noise, no
   // disturbance) run a compiled shape when every step of the solve reads its
@@ -613,7 +609,7 @@ amy_status amy_resolve(const amy_problem* p, uint64_t budget, Plan* pl) {
     memo_only_ok = plan_memo(p, q);
   }
   const bool fixed_ok = lanes_ok && (normal_masses ? amy_fixed_available(pl->dev) : memo_only_ok);
-  const bool fac_ok = fixed_ok && plain && mode == AMY_MODE_OTF && amy_fac_available(pl->dev);
+  const bool fac_ok = fixed_ok && normal_masses && mode == AMY_MODE_OTF && amy_fac_available(pl->dev);
   int64_t sum_l = 0;
   for (int i = 0; i < pl->dev.n; ++i) sum_l += pl->dev.L[i];
   const int64_t msz = pl->f64 ? 8 : 4;

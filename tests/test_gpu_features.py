@@ -261,13 +261,15 @@ def test_inputs_variant_full_robot_chained(orc):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_intersect_compiled_shape_is_bitwise_lanes(prec):
     """With the intersect rule the unicycle's windows are 6 x 6 x 3, a
-    compiled shape: AUTO runs it there (memoised tables), and its rows are
-    bitwise those of the run-time-window LANES sweep."""
+    compiled shape: AUTO runs the factored sweep there (its re-associated
+    sums are checked against the oracle with the parity cases), and the
+    per-state compiled-shape sweep (memoised tables) computes rows bitwise
+    those of the run-time-window LANES sweep."""
     import paper_2005_06191_amd as A
     p = CASES[f"unicycle-intersect-{prec}"]()
     say(f"[intersect fixed vs lanes] {prec}")
-    assert A.query(p)["variant"] == "fixed"
-    a = A.solve(p)
+    assert A.query(p)["variant"] == "factored"
+    a = A.solve(p.with_(variant="fixed"))
     b = A.solve(p.with_(variant="lanes"))
     assert a.info["variant"] == "fixed" and b.info["variant"] == "lanes"
     assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())

@@ -83,6 +83,10 @@ CASES = {
     "unicycle-even-fp32": lambda: _uni_even(precision="fp32"),
     "unicycle-even-fast-fp32": lambda: _uni_even(precision="fp32", u_hi=(3.0, 1.0)),
     "unicycle-y26-fp32": lambda: _uni_even(ny=26, precision="fp32"),
+    # the intersect window rule: 6 x 6 x 3 windows, relative tables keeping
+    # every cell that meets the cutting interval
+    "unicycle-patch-intersect-fp64": lambda: _uni_small(precision="fp64", window="intersect"),
+    "unicycle-even-intersect-fp32": lambda: _uni_even(precision="fp32", window="intersect"),
     "room-patch-fp32-otf": lambda: _room_small(precision="fp32"),
     "room-patch-fp64-otf": lambda: _room_small(precision="fp64"),
     "room-patch-fp64-stored": lambda: _room_small(precision="fp64", mode="stored"),
@@ -255,7 +259,8 @@ def test_fixed_shape_kernel_matches_generic(name):
 
 @pytest.mark.parametrize("name", ["unicycle-patch-fp32-otf", "unicycle-patch-fp64-otf", "unicycle-patch-reach-fp32",
                                   "unicycle-patch-fast-fp32", "unicycle-even-fp32", "unicycle-even-fast-fp32",
-                                  "unicycle-y26-fp32"])
+                                  "unicycle-y26-fp32", "unicycle-patch-intersect-fp64",
+                                  "unicycle-even-intersect-fp32"])
 def test_factored_sweep_matches_oracle_and_fixed(orc, name):
     """The factored sweep shares the outer contraction between inputs that
     differ only in the last digit: the window sum is re-associated, so it is

@@ -1525,12 +1525,13 @@ struct RelBox {
 };
 
 // LDS of a relative-box workgroup: the box, then per wave its U partial
-// sums and dimension 0's masses ([slot][lane] each), then the shared fast
+// sums behind L_{N-1} zero slots and dimension 0's masses ([slot][lane]
+// each), then the shared fast
 // digit tables; a first step that forms the row tails adds the heading's
 // FP64 memo entries of every fast digit ([digit][lane], 16-byte aligned).
 template <class SH, int U, int CY, class MT, class AT, class VI>
 static size_t relbox_lds_bytes(int nf, bool tail) {
-  const size_t b = (size_t)RelBox<SH, CY>::SIZE * sizeof(VI) + (size_t)CY * U * 64 * sizeof(AT) +
+  const size_t b = (size_t)RelBox<SH, CY>::SIZE * sizeof(VI) + (size_t)CY * (U + SH::L[SH::N - 1]) * 64 * sizeof(AT) +
                    (size_t)CY * SH::L[0] * 64 * sizeof(MT) + (size_t)nf * SH::L[SH::N - 1] * sizeof(MT) + (size_t)nf * 4;
   return tail ? ((b + 15) & ~(size_t)15) + (size_t)nf * 64 * 16 : b;
 }
@@ -1556,15 +1557,16 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
   constexpr int N = 3;
   constexpr int F = N - 1;
   constexpr int LF = SH::L[F];
-  static_assert(LF <= U && SH::LMAX <= REL_SLOTS, "relative-table sweep shape");
+  static_assert(2 * LF <= U && SH::LMAX <= REL_SLOTS, "relative-table sweep shape");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int wlo[2][CY];
   const int fd = P.m - 1, nf = P.ucount[fd], fm = P.rmult[F][fd];
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   VI* box = reinterpret_cast<VI*>(smem);
-  // the lane's U partial sums of one slow combination, read back by index
-  AT* asl = reinterpret_cast<AT*>(smem + BX::SIZE * sizeof(VI)) + w * U * 64 + lane;
-  unsigned char* after_asl = smem + BX::SIZE * sizeof(VI) + (size_t)CY * U * 64 * sizeof(AT);
+  // the lane's U partial sums of one slow combination, read back by index,
+  // after LF slots that hold zeros (slot t at asl[t * 64], t >= -LF)
+  AT* asl = reinterpret_cast<AT*>(smem + BX::SIZE * sizeof(VI)) + (w * (U + LF) + LF) * 64 + lane;
+  unsigned char* after_asl = smem + BX::SIZE * sizeof(VI) + (size_t)CY * (U + LF) * 64 * sizeof(AT);
   MT* t0 = reinterpret_cast<MT*>(after_asl) + w * SH::L[0] * 64 + lane;
   MT* thm = reinterpret_cast<MT*>(after_asl) + CY * SH::L[0] * 64;
   int32_t* thr = reinterpret_cast<int32_t*>(thm + nf * LF);
@@ -1683,6 +1685,12 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
   }
   int omin = nF;
   for (int f = 0; f < nf; ++f) omin = min(omin, min(max(j[F] + thr[f], 0), nF - LF));
+  // A index of a fast input's first kept cell is gl + thr[f]; slots past
+  // the heading count (t >= tv) and the LF slots before slot 0 read as
+  // zero, so every kept-cell product needs no mask
+  const int gl = j[F] - omin, tv = nF - omin;
+#pragma unroll
+  for (int k = 1; k <= LF; ++k) asl[-k * FIX_BLOCK] = AT(0);
   FixedRow<SH, MT> R;
   InputWalk iw;
   iw.reset();
@@ -1716,7 +1724,7 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
     else
       contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
 #pragma unroll
-    for (int t = 0; t < U; ++t) asl[t * FIX_BLOCK] = A[t];
+    for (int t = 0; t < U; ++t) asl[t * FIX_BLOCK] = t < tv ? A[t] : AT(0);
     if constexpr (TAIL) {
       // the row's kept-window and grid masses, multiplied in dimension
       // order as k_tail_memo does, so the max is the same bits
@@ -1727,16 +1735,19 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
       }
     }
     for (int f = 0; f < nf; ++f, ++u) {
-      const int g = j[F] + thr[f] - omin;  // A index of the first kept cell
+      // The window's origin is clamped to [0, nF - LF] over the fast
+      // inputs (omin is the smallest clamped origin), so the kept cells of
+      // an input lie in slots [g, g + LF) with g >= -LF after the clamp
+      // below: slots before 0 are below the grid, slots at or past tv
+      // beyond it.  g > U - LF happens only when omin = nF - LF, and then
+      // every slot from LF = tv on is zero, so clamping g to U - LF reads
+      // zeros as the unclamped window would have.  A zero term leaves the
+      // sum's bits as they are.
+      const int g = min(max(gl + thr[f], -LF), U - LF);
+      const AT* ap = asl + g * FIX_BLOCK;
       AT q = AT(0);
 #pragma unroll
-      for (int k = 0; k < LF; ++k) {
-        const int t = g + k;
-        const AT a = asl[min(max(t, 0), U - 1) * FIX_BLOCK];
-        const bool ok = t >= 0 && t < U && omin + t < nF;
-        const AT qk = fma_(AT(thm[f * LF + k]), a, q);
-        q = ok ? qk : q;
-      }
+      for (int k = 0; k < LF; ++k) q = fma_(AT(thm[f * LF + k]), ap[k * FIX_BLOCK], q);
       if (q > best) {
         best = q;
         arg = u;

@@ -1143,10 +1143,10 @@ __global__ void __launch_bounds__(FIX_BLOCK) k_sweep_memo(DevProblem P, const VI
 // moves the other half of the block onto the remaining ones.  Dense strides
 // (6, 36) put pairs of lanes on one bank: the profiler counted 39% of the
 // LDS cycles stalled on bank conflicts.
-template <class SH>
+template <class SH, int T0>
 struct StageBox {
   static_assert(SH::N == 5, "staged box: 5-D shapes");
-  static constexpr int C[5] = {SH::L[0] + 1, SH::L[1] + 3, SH::L[2] + 3, SH::L[3] + 3, SH::L[4] + 3};
+  static constexpr int C[5] = {SH::L[0] + T0, SH::L[1] + 3, SH::L[2] + 3, SH::L[3] + 3, SH::L[4] + 3};
   static constexpr int S3 = (C[4] + 7) / 8 * 8;
   // smallest stride >= C3 * S3 that is 20 mod 32
   static constexpr int S2 = C[3] * S3 + ((20 - C[3] * S3) % 32 + 32) % 32;
@@ -1176,7 +1176,7 @@ struct VLds {
   }
 };
 
-#define STAGE_BLOCK 256
+#define STAGE_BLOCK 256  // threads per cell of dimension 0 in a tile
 // The loop levels' masses are picked from registers with selects on the
 // (uniform) loop index rather than read from per-thread LDS slots: the sweep
 // is bound by LDS traffic, and the slots would also cost a fifth of the
@@ -1184,21 +1184,25 @@ struct VLds {
 #define STAGE_LL 0
 
 // TAIL: also the largest per-row FP64 tail over the launch into *tailmax.
-template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
-__global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const VI* __restrict__ Vin,
+// T0: cells of dimension 0 per tile (T0 x 256 threads); the threads of one
+// cell of dimension 0 stage a share of the box's rows of dimension 1.
+template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int T0>
+__global__ void __launch_bounds__(STAGE_BLOCK * T0) k_sweep_stage(DevProblem P, const VI* __restrict__ Vin,
                                                              VO* __restrict__ Vout,
                                                              const uint8_t* __restrict__ label,
                                                              int16_t* __restrict__ pol, const MT* __restrict__ rm,
                                                              const double* __restrict__ wg,
                                                              unsigned long long* __restrict__ tailmax) {
-  using BX = StageBox<SH>;
+  using BX = StageBox<SH, T0>;
   constexpr int N = 5;
+  static_assert(BX::C[1] % T0 == 0, "whole rows of dimension 1 per staging group");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int blo[N];
   VI* box = reinterpret_cast<VI*>(smem);
   MT* ll = STAGE_LL ? reinterpret_cast<MT*>(smem + ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15)) + threadIdx.x
                     : nullptr;
   const int t = threadIdx.x;
+  const int tp = t & (STAGE_BLOCK - 1), grp = t / STAGE_BLOCK;  // cell of a box plane; staging group
   int j[N];
   {
     uint32_t r = xcd_block(blockIdx.x, gridDim.x);
@@ -1209,21 +1213,24 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
       r /= td;
       j[d] = (int)(c * 4u);
     }
-    j[0] = (int)r;
+    j[0] = (int)r * T0 + grp;
     j[4] += t & 3;
     j[3] += (t >> 2) & 3;
     j[2] += (t >> 4) & 3;
-    j[1] += t >> 6;
+    j[1] += (t >> 6) & 3;
   }
   uint32_t s = 0;
 #pragma unroll
   for (int d = 0; d < N; ++d) s += (uint32_t)j[d] * (uint32_t)P.stride[d];
-  // this thread's cell of a box plane (dims 2..4) and its offset in V
+  // this thread's cell of a box plane (dims 2..4) and its offset in V; the
+  // group stages rows [grp C1 / T0, (grp + 1) C1 / T0) of dimension 1
   constexpr int C3C4 = BX::C[3] * BX::C[4];
-  const bool stager = t < BX::PLANE;
-  const uint32_t gt = (uint32_t)(t / C3C4) * (uint32_t)P.stride[2] +
-                      (uint32_t)((t / BX::C[4]) % BX::C[3]) * (uint32_t)P.stride[3] + (uint32_t)(t % BX::C[4]);
-  const int lt = (t / C3C4) * BX::S[2] + ((t / BX::C[4]) % BX::C[3]) * BX::S[3] + t % BX::C[4];
+  constexpr int R1 = BX::C[1] / T0;
+  const bool stager = tp < BX::PLANE;
+  const uint32_t gt = (uint32_t)(tp / C3C4) * (uint32_t)P.stride[2] +
+                      (uint32_t)((tp / BX::C[4]) % BX::C[3]) * (uint32_t)P.stride[3] + (uint32_t)(tp % BX::C[4]) +
+                      (uint32_t)(grp * R1) * (uint32_t)P.stride[1];
+  const int lt = (tp / C3C4) * BX::S[2] + ((tp / BX::C[4]) % BX::C[3]) * BX::S[3] + tp % BX::C[4] + grp * R1 * BX::S[1];
   const bool free = label[s] == LBL_FREE;
   if (!free) {
     Vout[s] = (label[s] == LBL_ONE) ? VO(1) : VO(0);
@@ -1272,14 +1279,15 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
       gb += (uint32_t)bl[d] * (uint32_t)P.stride[d];
     }
     if (stager) {
-      VI v[BX::PLANES];
+      constexpr int NP = BX::C[0] * R1;  // planes per staging group
+      VI v[NP];
 #pragma unroll
-      for (int p = 0; p < BX::PLANES; ++p)
+      for (int p = 0; p < NP; ++p)
         v[p] = vb.load((gb + gt) * (uint32_t)sizeof(VI),
-                       ((uint32_t)(p / BX::C[1]) * (uint32_t)P.stride[0] +
-                        (uint32_t)(p % BX::C[1]) * (uint32_t)P.stride[1]) * (uint32_t)sizeof(VI));
+                       ((uint32_t)(p / R1) * (uint32_t)P.stride[0] + (uint32_t)(p % R1) * (uint32_t)P.stride[1]) *
+                           (uint32_t)sizeof(VI));
 #pragma unroll
-      for (int p = 0; p < BX::PLANES; ++p) box[(p / BX::C[1]) * BX::S[0] + (p % BX::C[1]) * BX::S[1] + lt] = v[p];
+      for (int p = 0; p < NP; ++p) box[(p / R1) * BX::S[0] + (p % R1) * BX::S[1] + lt] = v[p];
     }
     if constexpr (STAGE_LL > 0) {
 #pragma unroll
@@ -1319,9 +1327,9 @@ __global__ void __launch_bounds__(STAGE_BLOCK) k_sweep_stage(DevProblem P, const
   }
 }
 
-template <int KIND, class SH, class MT, class VI>
-static size_t stage_lds_bytes() {
-  using BX = StageBox<SH>;
+template <int KIND, class SH, class MT, class VI, int T0>
+static constexpr size_t stage_lds_bytes() {
+  using BX = StageBox<SH, T0>;
   return ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) + (size_t)SH::BL * SH::LMAX * sizeof(MT) * STAGE_LL;
 }
 
@@ -1788,12 +1796,26 @@ struct FixedLaunch {
       if (ok) return true;
     }
     if constexpr (Staged<KIND, SH>::value) {
-      using BX = StageBox<SH>;
+      using BX = StageBox<SH, 1>;
       bool ok = true;
       for (int d = 0; d < SH::N; ++d) ok = ok && P.count[d] >= BX::C[d] && (d == 0 || P.count[d] % 4 == 0);
       return ok;
     }
     return false;
+  }
+  template <class MT, class AT, class VI, class VO, bool COMP, int T0>
+  static void stage(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                    const MT* rm, const double* wg, unsigned long long* tailmax, hipStream_t st) {
+    if constexpr (Staged<KIND, SH>::value) {
+      const dim3 gs((unsigned)(P.n_x / (STAGE_BLOCK * T0))), bs(STAGE_BLOCK * T0);
+      const size_t slds = stage_lds_bytes<KIND, SH, MT, VI, T0>();
+      if (tailmax)
+        hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP, true, T0>), gs, bs, slds, st, P,
+                           (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+      else
+        hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP, false, T0>), gs, bs, slds, st, P,
+                           (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+    }
   }
   template <class MT, class AT, class VI, class VO, bool COMP>
   static void go(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
@@ -1821,21 +1843,23 @@ struct FixedLaunch {
         }
       }
       if constexpr (Staged<KIND, SH>::value) {
-        using BX = StageBox<SH>;
+        using BX = StageBox<SH, 1>;
         bool ok = tables && P.tables == 2;
         for (int d = 0; d < SH::N; ++d) ok = ok && P.count[d] >= BX::C[d] && (d == 0 || P.count[d] % 4 == 0);
         if (ok) {
           const MT* rm = (const MT*)tables;
           const double* wg =
               (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(SH::LMAX), sizeof(MT)));
-          const dim3 gs((unsigned)(P.n_x / STAGE_BLOCK)), bs(STAGE_BLOCK);
-          const size_t slds = stage_lds_bytes<KIND, SH, MT, VI>();
-          if (tailmax)
-            hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP, true>), gs, bs, slds, st, P,
-                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
-          else
-            hipLaunchKernelGGL((k_sweep_stage<KIND, SH, MT, AT, VI, VO, COMP, false>), gs, bs, slds, st, P,
-                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+          // two cells of dimension 0 per tile where the count is even, the
+          // box stays within 64 KB (FP32 values) and its rows of dimension
+          // 1 split evenly between the two staging groups, else one
+          constexpr bool two_ok =
+              stage_lds_bytes<KIND, SH, MT, VI, 2>() <= 64 * 1024 && StageBox<SH, 2>::C[1] % 2 == 0;
+          if (two_ok && P.count[0] % 2 == 0 && P.count[0] >= StageBox<SH, 2>::C[0]) {
+            stage<MT, AT, VI, VO, COMP, (two_ok ? 2 : 1)>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
+            return;
+          }
+          stage<MT, AT, VI, VO, COMP, 1>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
           return;
         }
       }

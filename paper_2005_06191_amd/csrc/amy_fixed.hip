@@ -1347,10 +1347,19 @@ static constexpr size_t stage_lds_bytes() {
 // room, the box starts at the first state's origin clamped to the grid, a
 // window outside it is gathered from V, and the result is bitwise that of
 // the gather sweep.
-template <class SH>
+//
+// TW = 8 (a grid of exactly 8 cells in dimension 4): a workgroup of 8 waves
+// takes all 8 planes of states that share cells in dimensions 0 .. 3, and
+// its box spans the whole of dimension 4, so the 8 waves share one box
+// (8 / (L4 + 2) times the states per staged plane) and a CU holds two
+// such workgroups (16 waves, where the 2-wave workgroups' 52 KB allowed 6).
+// Wave w stages the box's planes at cell w of dimension 4.  The loop
+// levels' masses are then picked from registers (no per-thread LDS slots).
+template <class SH, int TW>
 struct PlaneBox {
   static_assert(SH::N == 7, "plane box: 7-D shapes");
-  static constexpr int C[7] = {SH::L[0], SH::L[1], SH::L[2], SH::L[3], SH::L[4] + 2, 8, 8};
+  static_assert(TW == 2 || TW == 8, "two planes per workgroup, or the whole 8-cell dimension 4");
+  static constexpr int C[7] = {SH::L[0], SH::L[1], SH::L[2], SH::L[3], TW == 8 ? 8 : SH::L[4] + 2, 8, 8};
   static constexpr int S[7] = {C[1] * C[2] * C[3] * C[4] * 64, C[2] * C[3] * C[4] * 64, C[3] * C[4] * 64,
                                C[4] * 64, 64, 8, 1};
   static constexpr int PLANES = C[0] * C[1] * C[2] * C[3] * C[4];
@@ -1364,26 +1373,33 @@ struct Planed {
 
 #define PLANE_BLOCK 128
 
-template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP, bool TAIL>
-__global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const VI* __restrict__ Vin,
-                                                             VO* __restrict__ Vout,
-                                                             const uint8_t* __restrict__ label,
-                                                             int16_t* __restrict__ pol, const MT* __restrict__ rm,
-                                                             const double* __restrict__ wg,
-                                                             unsigned long long* __restrict__ tailmax) {
-  using BX = PlaneBox<SH>;
+// Per-thread LDS slots of the loop levels' masses: the 2-wave workgroups'.
+template <int TW>
+struct PlaneLL {
+  static constexpr int value = TW == 2 ? PLANE_BLOCK : 0;
+};
+
+template <int KIND, class SH, class MT, class AT, class VI, class VO, bool COMP, bool TAIL, int TW>
+__global__ void __launch_bounds__(64 * TW) k_sweep_plane(DevProblem P, const VI* __restrict__ Vin,
+                                                         VO* __restrict__ Vout,
+                                                         const uint8_t* __restrict__ label,
+                                                         int16_t* __restrict__ pol, const MT* __restrict__ rm,
+                                                         const double* __restrict__ wg,
+                                                         unsigned long long* __restrict__ tailmax) {
+  using BX = PlaneBox<SH, TW>;
   constexpr int N = 7;
+  constexpr int LLN = PlaneLL<TW>::value;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int blo[N];
   VI* box = reinterpret_cast<VI*>(smem);
-  MT* ll = reinterpret_cast<MT*>(smem + ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15)) + threadIdx.x;
+  MT* ll = LLN ? reinterpret_cast<MT*>(smem + ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15)) + threadIdx.x : nullptr;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   int j[N];
   {
     uint32_t r = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t t4 = (uint32_t)P.count[4] / 2u;
-    j[4] = (int)(r % t4) * 2 + wave;
+    const uint32_t t4 = (uint32_t)P.count[4] / (uint32_t)TW;
+    j[4] = (int)(r % t4) * TW + wave;
     r /= t4;
 #pragma unroll
     for (int d = 3; d >= 0; --d) {
@@ -1450,32 +1466,63 @@ __global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const
     // plane is 64 consecutive values of V.  Fully unrolled, CH loads in
     // flight, then their LDS writes, and a scheduling barrier so that the
     // next chunk's loads are not hoisted above them (registers).
-    static_assert(BX::C[0] == 2, "one wave per half of the box along dimension 0");
-    constexpr int PER = BX::PLANES / 2, CH = 15;
-    static_assert(PER % CH == 0, "whole chunks");
-    const uint32_t gw = (gb + (uint32_t)wave * (uint32_t)P.stride[0] + (uint32_t)lane) * (uint32_t)sizeof(VI);
-    VI* bw = box + wave * PER * 64 + lane;
+    if constexpr (TW == 2) {
+      static_assert(BX::C[0] == 2, "one wave per half of the box along dimension 0");
+      constexpr int PER = BX::PLANES / 2, CH = 15;
+      static_assert(PER % CH == 0, "whole chunks");
+      const uint32_t gw = (gb + (uint32_t)wave * (uint32_t)P.stride[0] + (uint32_t)lane) * (uint32_t)sizeof(VI);
+      VI* bw = box + wave * PER * 64 + lane;
 #pragma unroll
-    for (int q0 = 0; q0 < PER; q0 += CH) {
-      VI v[CH];
+      for (int q0 = 0; q0 < PER; q0 += CH) {
+        VI v[CH];
 #pragma unroll
-      for (int q = 0; q < CH; ++q) {
-        const int i = q0 + q;
-        const int r4 = i % BX::C[4], r3 = (i / BX::C[4]) % BX::C[3], r2 = (i / (BX::C[4] * BX::C[3])) % BX::C[2];
-        const int r1 = i / (BX::C[4] * BX::C[3] * BX::C[2]);
-        const uint32_t po = (uint32_t)r1 * (uint32_t)P.stride[1] + (uint32_t)r2 * (uint32_t)P.stride[2] +
-                            (uint32_t)r3 * (uint32_t)P.stride[3] + (uint32_t)r4 * (uint32_t)P.stride[4];
-        v[q] = vb.load(gw, po * (uint32_t)sizeof(VI));
+        for (int q = 0; q < CH; ++q) {
+          const int i = q0 + q;
+          const int r4 = i % BX::C[4], r3 = (i / BX::C[4]) % BX::C[3], r2 = (i / (BX::C[4] * BX::C[3])) % BX::C[2];
+          const int r1 = i / (BX::C[4] * BX::C[3] * BX::C[2]);
+          const uint32_t po = (uint32_t)r1 * (uint32_t)P.stride[1] + (uint32_t)r2 * (uint32_t)P.stride[2] +
+                              (uint32_t)r3 * (uint32_t)P.stride[3] + (uint32_t)r4 * (uint32_t)P.stride[4];
+          v[q] = vb.load(gw, po * (uint32_t)sizeof(VI));
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) bw[(q0 + q) * 64] = v[q];
+        __builtin_amdgcn_sched_barrier(0);
       }
+    } else {
+      // wave w: the planes at box cell w of dimension 4, in box order
+      constexpr int PER = BX::PLANES / TW, CH = 12;
+      static_assert(BX::C[4] == TW && PER % CH == 0, "one wave per cell of dimension 4, whole chunks");
+      const uint32_t gw = (gb + (uint32_t)wave * (uint32_t)P.stride[4] + (uint32_t)lane) * (uint32_t)sizeof(VI);
+      VI* bw = box + wave * BX::S[4] + lane;
 #pragma unroll
-      for (int q = 0; q < CH; ++q) bw[(q0 + q) * 64] = v[q];
-      __builtin_amdgcn_sched_barrier(0);
+      for (int q0 = 0; q0 < PER; q0 += CH) {
+        VI v[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int i = q0 + q;  // (r0, r1, r2, r3), r3 fastest
+          const int r3 = i % BX::C[3], r2 = (i / BX::C[3]) % BX::C[2], r1 = (i / (BX::C[3] * BX::C[2])) % BX::C[1];
+          const int r0 = i / (BX::C[3] * BX::C[2] * BX::C[1]);
+          const uint32_t po = (uint32_t)r0 * (uint32_t)P.stride[0] + (uint32_t)r1 * (uint32_t)P.stride[1] +
+                              (uint32_t)r2 * (uint32_t)P.stride[2] + (uint32_t)r3 * (uint32_t)P.stride[3];
+          v[q] = vb.load(gw, po * (uint32_t)sizeof(VI));
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+          const int i = q0 + q;
+          const int r3 = i % BX::C[3], r2 = (i / BX::C[3]) % BX::C[2], r1 = (i / (BX::C[3] * BX::C[2])) % BX::C[1];
+          const int r0 = i / (BX::C[3] * BX::C[2] * BX::C[1]);
+          bw[r0 * BX::S[0] + r1 * BX::S[1] + r2 * BX::S[2] + r3 * BX::S[3]] = v[q];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
+    if constexpr (LLN > 0) {
 #pragma unroll
-    for (int d = 0; d < SH::BL; ++d)
+      for (int d = 0; d < SH::BL; ++d)
 #pragma unroll
-      for (int k = 0; k < SH::LMAX; ++k)
-        if (k < SH::L[d]) ll[(d * SH::LMAX + k) * PLANE_BLOCK] = R.m[d][k];
+        for (int k = 0; k < SH::LMAX; ++k)
+          if (k < SH::L[d]) ll[(d * SH::LMAX + k) * LLN] = R.m[d][k];
+    }
     __syncthreads();
     if (free) {
       bool in = true;
@@ -1488,9 +1535,9 @@ __global__ void __launch_bounds__(PLANE_BLOCK) k_sweep_plane(DevProblem P, const
       }
       AT q;
       if (in)
-        q = contract_fixed<0, SH, MT, AT, VLds<VI, BX>, COMP, PLANE_BLOCK>(P, R, vl, lo * (uint32_t)sizeof(VI), 0u, ll);
+        q = contract_fixed<0, SH, MT, AT, VLds<VI, BX>, COMP, LLN>(P, R, vl, lo * (uint32_t)sizeof(VI), 0u, ll);
       else
-        q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP, PLANE_BLOCK>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
+        q = contract_fixed<0, SH, MT, AT, VBuf<VI>, COMP, LLN>(P, R, vb, base * (uint32_t)sizeof(VI), 0u, ll);
       if (q > best) {
         best = q;
         arg = u;
@@ -1790,7 +1837,7 @@ struct FixedLaunch {
   static bool memo_complete(const DevProblem& P, bool f64) {
     if (!matches(P) || SH::LMAX > REL_SLOTS) return false;
     if constexpr (Planed<KIND, SH>::value) {
-      using BX = PlaneBox<SH>;
+      using BX = PlaneBox<SH, 2>;
       bool ok = !f64 && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0;
       for (int d = 0; d < 5; ++d) ok = ok && P.count[d] >= BX::C[d];
       if (ok) return true;
@@ -1817,28 +1864,39 @@ struct FixedLaunch {
                            (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
     }
   }
+  template <class MT, class AT, class VI, class VO, bool COMP, int TW>
+  static void plane(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
+                    const MT* rm, const double* wg, unsigned long long* tailmax, hipStream_t st) {
+    if constexpr (Planed<KIND, SH>::value) {
+      using BX = PlaneBox<SH, TW>;
+      const dim3 gs((unsigned)(P.n_x / (64 * TW))), bs(64 * TW);
+      const size_t slds = ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) +
+                          (size_t)SH::BL * SH::LMAX * sizeof(MT) * PlaneLL<TW>::value;
+      if (tailmax)
+        hipLaunchKernelGGL((k_sweep_plane<KIND, SH, MT, AT, VI, VO, COMP, true, TW>), gs, bs, slds, st, P,
+                           (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+      else
+        hipLaunchKernelGGL((k_sweep_plane<KIND, SH, MT, AT, VI, VO, COMP, false, TW>), gs, bs, slds, st, P,
+                           (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+    }
+  }
   template <class MT, class AT, class VI, class VO, bool COMP>
   static void go(const DevProblem& P, const void* Vin, void* Vout, const uint8_t* label, int16_t* pol,
                  unsigned long long* tailmax, const void* tables, hipStream_t st) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
     if constexpr (SH::LMAX <= REL_SLOTS) {
       if constexpr (Planed<KIND, SH>::value && sizeof(VI) == 4) {
-        using BX = PlaneBox<SH>;
+        using BX = PlaneBox<SH, 2>;
         bool ok = tables && P.tables == 2 && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0;
         for (int d = 0; d < 5; ++d) ok = ok && P.count[d] >= BX::C[d];
         if (ok) {
           const MT* rm = (const MT*)tables;
           const double* wg =
               (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(SH::LMAX), sizeof(MT)));
-          const dim3 gs((unsigned)(P.n_x / PLANE_BLOCK)), bs(PLANE_BLOCK);
-          const size_t slds = ((BX::SIZE * sizeof(VI) + 15) & ~(size_t)15) +
-                              (size_t)SH::BL * SH::LMAX * sizeof(MT) * PLANE_BLOCK;
-          if (tailmax)
-            hipLaunchKernelGGL((k_sweep_plane<KIND, SH, MT, AT, VI, VO, COMP, true>), gs, bs, slds, st, P,
-                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
-          else
-            hipLaunchKernelGGL((k_sweep_plane<KIND, SH, MT, AT, VI, VO, COMP, false>), gs, bs, slds, st, P,
-                               (const VI*)Vin, (VO*)Vout, label, pol, rm, wg, tailmax);
+          // the whole 8-cell dimension 4 in one workgroup where the grid has
+          // exactly that (its box, 72 KB in FP32, leaves room for two per CU)
+          if (P.count[4] == 8) plane<MT, AT, VI, VO, COMP, 8>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
+          else plane<MT, AT, VI, VO, COMP, 2>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
           return;
         }
       }

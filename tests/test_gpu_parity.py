@@ -59,12 +59,13 @@ def _room8(**kw):
     return p.with_(lo=lo, h=h, count=cnt, horizon=kw.pop("horizon", 6), name="room-8^5", **kw)
 
 
-def _vehicle_planes(**kw):
-    # the vehicle workload's cell widths, noise and cutoff on a 2x2x3x3x6 x 8x8
+def _vehicle_planes(n4=6, **kw):
+    # the vehicle workload's cell widths, noise and cutoff on a 2x2x3x3xn4 x 8x8
     # sub-box: whole yaw-rate / slip-angle planes, so the memoised steps stage
-    # planes of V in LDS
+    # planes of V in LDS (with n4 = 8 heading cells, one workgroup takes all
+    # eight planes of states that share the other cells)
     p = W.vehicle7d()
-    return p.with_(lo=(-2.5, -2.5, -0.15, -0.75, -0.225, -0.4, -0.04), count=(2, 2, 3, 3, 6, 8, 8),
+    return p.with_(lo=(-2.5, -2.5, -0.15, -0.75, -0.225, -0.4, -0.04), count=(2, 2, 3, 3, n4, 8, 8),
                    horizon=kw.pop("horizon", 4), u_count=(3, 3), name="vehicle7-planes", **kw)
 
 
@@ -99,6 +100,9 @@ CASES = {
     # write their value and still take part in every staging pass
     "room-8^5-safebox-fp32": lambda: _room8(precision="fp32", safe=W.box((19.65,) * 5, (20.3,) * 5, 5)),
     "vehicle7-planes-fp32": lambda: _vehicle_planes(precision="fp32"),
+    "vehicle7-planes8-fp32": lambda: _vehicle_planes(n4=8, precision="fp32"),
+    "vehicle7-planes8-tau0.3-fp32": lambda: _vehicle_planes(n4=8, precision="fp32",
+                                                            params=(0.3,) + W.VEHICLE7_BMW320I[1:]),
     # time step 0.3: about 7% of the windows spread past the staged planes
     # in the heading and are gathered from V instead
     "vehicle7-planes-tau0.3-fp32": lambda: _vehicle_planes(precision="fp32",
@@ -241,7 +245,8 @@ def test_full_size_separable_5d(orc):
                                   "linear2d-full-fp32-otf", "room-patch-fp64-otf", "room-8^5-fp32-otf",
                                   "room-8^5-fp64-otf", "room-8^5-coupled-fp32", "room-8^5-safebox-fp32",
                                   "vehicle7-planes-fp32",
-                                  "vehicle7-planes-tau0.3-fp32"])
+                                  "vehicle7-planes-tau0.3-fp32", "vehicle7-planes8-fp32",
+                                  "vehicle7-planes8-tau0.3-fp32"])
 def test_fixed_shape_kernel_matches_generic(name):
     """The compiled-window-shape sweep does the generic sweep's arithmetic in
     the same order: results are bitwise equal."""

@@ -1838,7 +1838,8 @@ struct FixedLaunch {
     if (!matches(P) || SH::LMAX > REL_SLOTS) return false;
     if constexpr (Planed<KIND, SH>::value) {
       using BX = PlaneBox<SH, 2>;
-      bool ok = !f64 && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0;
+      // FP64 boxes only in the 8-wave form (147 KB of LDS)
+      bool ok = (!f64 || P.count[4] == 8) && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0;
       for (int d = 0; d < 5; ++d) ok = ok && P.count[d] >= BX::C[d];
       if (ok) return true;
     }
@@ -1885,9 +1886,10 @@ struct FixedLaunch {
                  unsigned long long* tailmax, const void* tables, hipStream_t st) {
     const dim3 g((unsigned)((P.n_x + FIX_BLOCK - 1) / FIX_BLOCK)), b(FIX_BLOCK);
     if constexpr (SH::LMAX <= REL_SLOTS) {
-      if constexpr (Planed<KIND, SH>::value && sizeof(VI) == 4) {
+      if constexpr (Planed<KIND, SH>::value) {
         using BX = PlaneBox<SH, 2>;
-        bool ok = tables && P.tables == 2 && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0;
+        bool ok = tables && P.tables == 2 && P.count[5] == 8 && P.count[6] == 8 && P.count[4] % 2 == 0 &&
+                  (sizeof(VI) == 4 || P.count[4] == 8);
         for (int d = 0; d < 5; ++d) ok = ok && P.count[d] >= BX::C[d];
         if (ok) {
           const MT* rm = (const MT*)tables;
@@ -1895,8 +1897,10 @@ struct FixedLaunch {
               (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(SH::LMAX), sizeof(MT)));
           // the whole 8-cell dimension 4 in one workgroup where the grid has
           // exactly that (its box, 72 KB in FP32, leaves room for two per CU)
+          // (an FP64 box of the 2-wave form would be 90 KB for 2 waves; the
+          // 8-wave one, 147 KB, holds one workgroup per CU)
           if (P.count[4] == 8) plane<MT, AT, VI, VO, COMP, 8>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
-          else plane<MT, AT, VI, VO, COMP, 2>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
+          else if constexpr (sizeof(VI) == 4) plane<MT, AT, VI, VO, COMP, 2>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
           return;
         }
       }

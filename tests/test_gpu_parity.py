@@ -101,6 +101,7 @@ CASES = {
     "room-8^5-safebox-fp32": lambda: _room8(precision="fp32", safe=W.box((19.65,) * 5, (20.3,) * 5, 5)),
     "vehicle7-planes-fp32": lambda: _vehicle_planes(precision="fp32"),
     "vehicle7-planes8-fp32": lambda: _vehicle_planes(n4=8, precision="fp32"),
+    "vehicle7-planes8-fp64": lambda: _vehicle_planes(n4=8, precision="fp64"),
     "vehicle7-planes8-tau0.3-fp32": lambda: _vehicle_planes(n4=8, precision="fp32",
                                                             params=(0.3,) + W.VEHICLE7_BMW320I[1:]),
     # time step 0.3: about 7% of the windows spread past the staged planes
@@ -246,7 +247,7 @@ def test_full_size_separable_5d(orc):
                                   "room-8^5-fp64-otf", "room-8^5-coupled-fp32", "room-8^5-safebox-fp32",
                                   "vehicle7-planes-fp32",
                                   "vehicle7-planes-tau0.3-fp32", "vehicle7-planes8-fp32",
-                                  "vehicle7-planes8-tau0.3-fp32"])
+                                  "vehicle7-planes8-tau0.3-fp32", "vehicle7-planes8-fp64"])
 def test_fixed_shape_kernel_matches_generic(name):
     """The compiled-window-shape sweep does the generic sweep's arithmetic in
     the same order: results are bitwise equal."""

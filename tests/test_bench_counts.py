@@ -1,8 +1,7 @@
-"""The per-row work counts bench.py prices its roofline fractions on,
-checked against the same sums written out by hand (the window contraction
-done dimension by dimension, Sec. 5; the factored contraction shared by the
-fast input's values) and against brute-force counts of the multiply-adds a
-literal loop nest would issue."""
+"""The per-row work counts bench.py prices its roofline fractions on (the
+window contraction done dimension by dimension; the factored contraction
+shared by the fast input's values), checked against values written out by
+hand and against counts of the multiply-adds a literal loop nest issues."""
 import itertools
 import math
 import os

@@ -1351,7 +1351,8 @@ static constexpr size_t stage_lds_bytes() {
 // TW = 8 (a grid of exactly 8 cells in dimension 4): a workgroup of 8 waves
 // takes all 8 planes of states that share cells in dimensions 0 .. 3, and
 // its box spans the whole of dimension 4, so the 8 waves share one box
-// (8 / (L4 + 2) times the states per staged plane) and a CU holds two
+// (a staged plane serves 8 planes of states over 8 box planes in dimension
+// 4, where it served 2 over L4 + 2) and a CU holds two
 // such workgroups (16 waves, where the 2-wave workgroups' 52 KB allowed 6).
 // Wave w stages the box's planes at cell w of dimension 4.  The loop
 // levels' masses are then picked from registers (no per-thread LDS slots).
@@ -1720,104 +1721,104 @@ __global__ void __launch_bounds__(64 * CY) k_sweep_relbox(DevProblem P, const VI
   }
   __syncthreads();
   double tmax = 0.0;
-  do {
-  if (!free) break;  // no barrier follows
-  const VLds<VI, BX> vl{box};
-  // the row tails' context entries of dimensions 0 and 1
-  int64_t tb[2] = {0, 0};
-  if constexpr (TAIL) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      int64_t cx = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (k < mt.cn[i]) {
-          const int d = mt.ctx[i][k];
-          cx += (int64_t)(d == 0 ? j[0] : d == 1 ? j[1] : j[2]) * mt.mult[i][k];
-        }
-      tb[i] = mt.off[i] + cx * mt.rc[i];
-    }
-  }
-  int omin = nF;
-  for (int f = 0; f < nf; ++f) omin = min(omin, min(max(j[F] + thr[f], 0), nF - LF));
-  // A index of a fast input's first kept cell is gl + thr[f]; slots past
-  // the heading count (t >= tv) and the LF slots before slot 0 read as
-  // zero, so every kept-cell product needs no mask
-  const int gl = j[F] - omin, tv = nF - omin;
-#pragma unroll
-  for (int k = 1; k <= LF; ++k) asl[-k * FIX_BLOCK] = AT(0);
-  FixedRow<SH, MT> R;
-  InputWalk iw;
-  iw.reset();
-  AT best = AT(-1);
-  int arg = 0, u = 0;
-  for (int sc = 0; sc < nslow; ++sc) {
-    uint32_t base = (uint32_t)omin;
-    int r[N];
-    double2 ex, ey;
+  do {  // the free lanes' rows; the others skip to the tail reduction
+    if (!free) break;  // no barrier follows
+    const VLds<VI, BX> vl{box};
+    // the row tails' context entries of dimensions 0 and 1
+    int64_t tb[2] = {0, 0};
     if constexpr (TAIL) {
-      // this slow combination's entries of dimensions 0 and 1, loaded now
-      // and used after the contraction
-      int64_t e0 = tb[0], e1 = tb[1];
 #pragma unroll
-      for (int k = 0; k < AMY_MAXI; ++k)
+      for (int i = 0; i < 2; ++i) {
+        int64_t cx = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (k < mt.cn[i]) {
+            const int d = mt.ctx[i][k];
+            cx += (int64_t)(d == 0 ? j[0] : d == 1 ? j[1] : j[2]) * mt.mult[i][k];
+          }
+        tb[i] = mt.off[i] + cx * mt.rc[i];
+      }
+    }
+    int omin = nF;
+    for (int f = 0; f < nf; ++f) omin = min(omin, min(max(j[F] + thr[f], 0), nF - LF));
+    // A index of a fast input's first kept cell is gl + thr[f]; slots past
+    // the heading count (t >= tv) and the LF slots before slot 0 read as
+    // zero, so every kept-cell product needs no mask
+    const int gl = j[F] - omin, tv = nF - omin;
+#pragma unroll
+    for (int k = 1; k <= LF; ++k) asl[-k * FIX_BLOCK] = AT(0);
+    FixedRow<SH, MT> R;
+    InputWalk iw;
+    iw.reset();
+    AT best = AT(-1);
+    int arg = 0, u = 0;
+    for (int sc = 0; sc < nslow; ++sc) {
+      uint32_t base = (uint32_t)omin;
+      int r[N];
+      double2 ex, ey;
+      if constexpr (TAIL) {
+        // this slow combination's entries of dimensions 0 and 1, loaded now
+        // and used after the contraction
+        int64_t e0 = tb[0], e1 = tb[1];
+#pragma unroll
+        for (int k = 0; k < AMY_MAXI; ++k)
+          if (k < fd) {
+            e0 += (int64_t)iw.dig[k] * P.rmult[0][k];
+            e1 += (int64_t)iw.dig[k] * P.rmult[1][k];
+          }
+        ex = mt.wg[e0];
+        ey = mt.wg[e1];
+      }
+      rel_load<0, SH, MT>(P, iw, j, rm, rlo, R, r);
+      rel_place<0, SH, MT>(P, r, t0, R, base);
+      const int o0 = min(max(r[0], 0), P.count[0] - SH::L[0]) - b0;
+      const int o1 = min(max(r[1], 0), P.count[1] - SH::L[1]) - b1;
+      AT A[U];
+      if (o0 >= 0 && o0 + SH::L[0] <= BX::C[0] && o1 >= 0 && o1 + SH::L[1] <= BX::C[1])
+        contract_fac<SH, U, MT, AT, VLds<VI, BX>, COMP>(
+            P, R, t0, vl, ((uint32_t)o0 * BX::S[0] + (uint32_t)o1 * BX::S[1] + (uint32_t)omin) * (uint32_t)sizeof(VI), A);
+      else
+        contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
+#pragma unroll
+      for (int t = 0; t < U; ++t) asl[t * FIX_BLOCK] = t < tv ? A[t] : AT(0);
+      if constexpr (TAIL) {
+        // the row's kept-window and grid masses, multiplied in dimension
+        // order as k_tail_memo does, so the max is the same bits
+        const double w01 = ex.x * ey.x, g01 = ex.y * ey.y;
+        for (int f = 0; f < nf; ++f) {
+          const double2 ef = fent[f * 64 + lane];
+          tmax = fmax(tmax, g01 * ef.y - w01 * ef.x);
+        }
+      }
+      for (int f = 0; f < nf; ++f, ++u) {
+        // The window's origin is clamped to [0, nF - LF] over the fast
+        // inputs (omin is the smallest clamped origin), so the kept cells of
+        // an input lie in slots [g, g + LF) with g >= -LF after the clamp
+        // below: slots before 0 are below the grid, slots at or past tv
+        // beyond it.  g > U - LF happens only when omin = nF - LF, and then
+        // every slot from LF = tv on is zero, so clamping g to U - LF reads
+        // zeros as the unclamped window would have.  A zero term leaves the
+        // sum's bits as they are.
+        const int g = min(max(gl + thr[f], -LF), U - LF);
+        const AT* ap = asl + g * FIX_BLOCK;
+        AT q = AT(0);
+#pragma unroll
+        for (int k = 0; k < LF; ++k) q = fma_(AT(thm[f * LF + k]), ap[k * FIX_BLOCK], q);
+        if (q > best) {
+          best = q;
+          arg = u;
+        }
+      }
+#pragma unroll
+      for (int k = AMY_MAXI - 1; k >= 0; --k) {
         if (k < fd) {
-          e0 += (int64_t)iw.dig[k] * P.rmult[0][k];
-          e1 += (int64_t)iw.dig[k] * P.rmult[1][k];
+          if (++iw.dig[k] < P.ucount[k]) break;
+          iw.dig[k] = 0;
         }
-      ex = mt.wg[e0];
-      ey = mt.wg[e1];
-    }
-    rel_load<0, SH, MT>(P, iw, j, rm, rlo, R, r);
-    rel_place<0, SH, MT>(P, r, t0, R, base);
-    const int o0 = min(max(r[0], 0), P.count[0] - SH::L[0]) - b0;
-    const int o1 = min(max(r[1], 0), P.count[1] - SH::L[1]) - b1;
-    AT A[U];
-    if (o0 >= 0 && o0 + SH::L[0] <= BX::C[0] && o1 >= 0 && o1 + SH::L[1] <= BX::C[1])
-      contract_fac<SH, U, MT, AT, VLds<VI, BX>, COMP>(
-          P, R, t0, vl, ((uint32_t)o0 * BX::S[0] + (uint32_t)o1 * BX::S[1] + (uint32_t)omin) * (uint32_t)sizeof(VI), A);
-    else
-      contract_fac<SH, U, MT, AT, VBuf<VI>, COMP>(P, R, t0, vb, base * (uint32_t)sizeof(VI), A);
-#pragma unroll
-    for (int t = 0; t < U; ++t) asl[t * FIX_BLOCK] = t < tv ? A[t] : AT(0);
-    if constexpr (TAIL) {
-      // the row's kept-window and grid masses, multiplied in dimension
-      // order as k_tail_memo does, so the max is the same bits
-      const double w01 = ex.x * ey.x, g01 = ex.y * ey.y;
-      for (int f = 0; f < nf; ++f) {
-        const double2 ef = fent[f * 64 + lane];
-        tmax = fmax(tmax, g01 * ef.y - w01 * ef.x);
       }
     }
-    for (int f = 0; f < nf; ++f, ++u) {
-      // The window's origin is clamped to [0, nF - LF] over the fast
-      // inputs (omin is the smallest clamped origin), so the kept cells of
-      // an input lie in slots [g, g + LF) with g >= -LF after the clamp
-      // below: slots before 0 are below the grid, slots at or past tv
-      // beyond it.  g > U - LF happens only when omin = nF - LF, and then
-      // every slot from LF = tv on is zero, so clamping g to U - LF reads
-      // zeros as the unclamped window would have.  A zero term leaves the
-      // sum's bits as they are.
-      const int g = min(max(gl + thr[f], -LF), U - LF);
-      const AT* ap = asl + g * FIX_BLOCK;
-      AT q = AT(0);
-#pragma unroll
-      for (int k = 0; k < LF; ++k) q = fma_(AT(thm[f * LF + k]), ap[k * FIX_BLOCK], q);
-      if (q > best) {
-        best = q;
-        arg = u;
-      }
-    }
-#pragma unroll
-    for (int k = AMY_MAXI - 1; k >= 0; --k) {
-      if (k < fd) {
-        if (++iw.dig[k] < P.ucount[k]) break;
-        iw.dig[k] = 0;
-      }
-    }
-  }
-  Vout[s] = VO(best);
-  if (pol) pol[s] = (int16_t)arg;
+    Vout[s] = VO(best);
+    if (pol) pol[s] = (int16_t)arg;
   } while (false);
   if constexpr (TAIL) wave_max_to(tmax, tailmax);
 }

@@ -1195,7 +1195,10 @@ __global__ void __launch_bounds__(STAGE_BLOCK * T0) k_sweep_stage(DevProblem P, 
                                                              unsigned long long* __restrict__ tailmax) {
   using BX = StageBox<SH, T0>;
   constexpr int N = 5;
-  static_assert(BX::C[1] % T0 == 0, "whole rows of dimension 1 per staging group");
+  // the staging groups split the box's rows of dimension 1, or of
+  // dimension 0 where dimension 1's do not divide evenly
+  constexpr bool SPLIT1 = BX::C[1] % T0 == 0;
+  static_assert(SPLIT1 || BX::C[0] % T0 == 0, "whole rows per staging group");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int blo[N];
   VI* box = reinterpret_cast<VI*>(smem);
@@ -1223,14 +1226,16 @@ __global__ void __launch_bounds__(STAGE_BLOCK * T0) k_sweep_stage(DevProblem P, 
 #pragma unroll
   for (int d = 0; d < N; ++d) s += (uint32_t)j[d] * (uint32_t)P.stride[d];
   // this thread's cell of a box plane (dims 2..4) and its offset in V; the
-  // group stages rows [grp C1 / T0, (grp + 1) C1 / T0) of dimension 1
+  // group stages an R0 x R1 block of the box's (dim 0, dim 1) planes
   constexpr int C3C4 = BX::C[3] * BX::C[4];
-  constexpr int R1 = BX::C[1] / T0;
+  constexpr int R0 = SPLIT1 ? BX::C[0] : BX::C[0] / T0, R1 = SPLIT1 ? BX::C[1] / T0 : BX::C[1];
+  const int g0 = SPLIT1 ? 0 : grp * R0, g1 = SPLIT1 ? grp * R1 : 0;  // the block's first plane
   const bool stager = tp < BX::PLANE;
   const uint32_t gt = (uint32_t)(tp / C3C4) * (uint32_t)P.stride[2] +
                       (uint32_t)((tp / BX::C[4]) % BX::C[3]) * (uint32_t)P.stride[3] + (uint32_t)(tp % BX::C[4]) +
-                      (uint32_t)(grp * R1) * (uint32_t)P.stride[1];
-  const int lt = (tp / C3C4) * BX::S[2] + ((tp / BX::C[4]) % BX::C[3]) * BX::S[3] + tp % BX::C[4] + grp * R1 * BX::S[1];
+                      (uint32_t)g0 * (uint32_t)P.stride[0] + (uint32_t)g1 * (uint32_t)P.stride[1];
+  const int lt = (tp / C3C4) * BX::S[2] + ((tp / BX::C[4]) % BX::C[3]) * BX::S[3] + tp % BX::C[4] + g0 * BX::S[0] +
+                 g1 * BX::S[1];
   const bool free = label[s] == LBL_FREE;
   if (!free) {
     Vout[s] = (label[s] == LBL_ONE) ? VO(1) : VO(0);
@@ -1279,7 +1284,7 @@ __global__ void __launch_bounds__(STAGE_BLOCK * T0) k_sweep_stage(DevProblem P, 
       gb += (uint32_t)bl[d] * (uint32_t)P.stride[d];
     }
     if (stager) {
-      constexpr int NP = BX::C[0] * R1;  // planes per staging group
+      constexpr int NP = R0 * R1;  // planes per staging group
       VI v[NP];
 #pragma unroll
       for (int p = 0; p < NP; ++p)
@@ -1915,9 +1920,9 @@ struct FixedLaunch {
               (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(SH::LMAX), sizeof(MT)));
           // two cells of dimension 0 per tile where the count is even, the
           // box stays within 64 KB (FP32 values) and its rows of dimension
-          // 1 split evenly between the two staging groups, else one
-          constexpr bool two_ok =
-              stage_lds_bytes<KIND, SH, MT, VI, 2>() <= 64 * 1024 && StageBox<SH, 2>::C[1] % 2 == 0;
+          // 1 or 0 split evenly between the two staging groups, else one
+          constexpr bool two_ok = stage_lds_bytes<KIND, SH, MT, VI, 2>() <= 64 * 1024 &&
+                                  (StageBox<SH, 2>::C[1] % 2 == 0 || StageBox<SH, 2>::C[0] % 2 == 0);
           if (two_ok && P.count[0] % 2 == 0 && P.count[0] >= StageBox<SH, 2>::C[0]) {
             stage<MT, AT, VI, VO, COMP, (two_ok ? 2 : 1)>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
             return;

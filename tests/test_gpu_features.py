@@ -275,3 +275,20 @@ def test_intersect_compiled_shape_is_bitwise_lanes(prec):
     assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())
     assert np.array_equal(a.policy.cpu().numpy(), b.policy.cpu().numpy())
     assert a.info["max_row_tail"] == b.info["max_row_tail"]
+
+
+@pytest.mark.parametrize("name", ["room8-beta-fp32-memo", "room8-beta-fp32-memo-coupled", "room8-uniform-fp64-memo"])
+def test_general_noise_staged_is_bitwise_lanes(name):
+    """Beta and uniform noise on the 8^5 room grid: the staged sweep on
+    memoised general-noise tables (two-cell tiles, the 2^5 shape's box
+    staged by two groups along dimension 0) computes rows bitwise those of
+    the run-time-window LANES sweep, which builds the same masses per row."""
+    import paper_2005_06191_amd as A
+    p = CASES[name]()
+    say(f"[general noise fixed vs lanes] {name}")
+    a = A.solve(p.with_(variant="fixed"))
+    b = A.solve(p.with_(variant="lanes"))
+    assert a.info["variant"] == "fixed" and b.info["variant"] == "lanes"
+    assert np.array_equal(a.V.cpu().numpy(), b.V.cpu().numpy())
+    assert np.array_equal(a.policy.cpu().numpy(), b.policy.cpu().numpy())
+    assert a.info["max_row_tail"] == b.info["max_row_tail"]

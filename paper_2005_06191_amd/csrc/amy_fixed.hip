@@ -1918,10 +1918,11 @@ struct FixedLaunch {
           const MT* rm = (const MT*)tables;
           const double* wg =
               (const double*)((const char*)tables + memo_wg_offset(P, amy_memo_rec(SH::LMAX), sizeof(MT)));
-          // two cells of dimension 0 per tile where the count is even, the
-          // box stays within 64 KB (FP32 values) and its rows of dimension
-          // 1 or 0 split evenly between the two staging groups, else one
-          constexpr bool two_ok = stage_lds_bytes<KIND, SH, MT, VI, 2>() <= 64 * 1024 &&
+          // two cells of dimension 0 per tile where the count is even, two
+          // such boxes fit a CU's 160 KB of LDS (80 KB each: the FP64 3^5
+          // box is 75 KB) and the box's rows of dimension 1 or 0 split
+          // evenly between the two staging groups, else one
+          constexpr bool two_ok = stage_lds_bytes<KIND, SH, MT, VI, 2>() <= 80 * 1024 &&
                                   (StageBox<SH, 2>::C[1] % 2 == 0 || StageBox<SH, 2>::C[0] % 2 == 0);
           if (two_ok && P.count[0] % 2 == 0 && P.count[0] >= StageBox<SH, 2>::C[0]) {
             stage<MT, AT, VI, VO, COMP, (two_ok ? 2 : 1)>(P, Vin, Vout, label, pol, rm, wg, tailmax, st);
